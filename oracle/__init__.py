@@ -1,0 +1,257 @@
+"""FP64 CPU oracle for generalized two-dimensional correlation analysis.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check in
+``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import this
+package.  It shares no code with the HIP product path (``paper_1808_00685_amd``)
+and never imports it; the product path never imports this package.
+
+The numerical work lives in ``oracle.c`` (plain C, double precision, natural
+summation order, OpenMP over independent output rows).  This module only
+marshals numpy arrays and combines the paper's normalization readings:
+
+* ``hilbert="noda"``: Noda's direct formulas, Sec. 2 Eqs. (disHTsyn), (disHT),
+  (HilbNoda), (disHTasyn) -- synchronous  Y1^T Y2 / (m-1), asynchronous
+  Y1^T N Y2 / (m-1) with the Hilbert-Noda matrix N.
+* ``hilbert="circular"``: the m-point Fourier route, Sec. 2 Eqs. (disFT),
+  (disint2d), (symmeFT) with the Hermitian-complete half spectrum of Sec. 4.2.
+* Normalization ``norm`` is the factor cF applied to the Hermitian-weighted
+  Fourier sum (Sec. 4.2, the ``Norm`` argument): "noda" cF = 1/(m(m-1)), which
+  makes the synchronous spectrum equal Y^T Y/(m-1); "paper" cF = 1/(pi(m-1)),
+  the paper's default ``Norm``; "custom" cF = ``norm_value``.  Since the
+  weighted Fourier sum of real data is m times the time-domain sum (Parseval),
+  the direct route under norm cF is the "noda" result times cF*m*(m-1).
+
+Parity pins (tests/test_oracle_pins.py) tie every function here to closed
+forms, invariants and an independent padded-Fourier algorithm.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+GCC_CMD = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-o", _LIB_PATH, _SRC, "-lm"]
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so next to it (plain gcc, no HIP)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+        subprocess.run(GCC_CMD, check=True)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lp = ctypes.POINTER(ctypes.c_long)
+        cl = ctypes.c_long
+        L.oracle_dynamic.argtypes = [cl, cl, dp, cl, dp, dp, dp]
+        L.oracle_hilbert_noda.argtypes = [cl, dp]
+        L.oracle_noda_transform.argtypes = [cl, cl, dp, dp]
+        L.oracle_corr_ht.argtypes = [cl, cl, cl, dp, dp, dp, dp]
+        L.oracle_corr_ht_entries.argtypes = [cl, cl, cl, dp, dp, cl, lp, lp, dp, dp]
+        L.oracle_dft.argtypes = [cl, cl, dp, dp, dp]
+        L.oracle_corr_ft_circular.argtypes = [cl, cl, cl, dp, dp, ctypes.c_double, dp, dp]
+        L.oracle_corr_ft_padded.argtypes = [cl, cl, cl, dp, dp, cl, dp, dp]
+        L.oracle_corr_ft_circular_entries.argtypes = [cl, cl, cl, dp, dp, ctypes.c_double,
+                                                      cl, lp, lp, dp, dp]
+        L.oracle_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _lp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
+
+
+# --------------------------------------------------------------------------
+# Building blocks (each follows one equation of the paper)
+# --------------------------------------------------------------------------
+def dynamic(S, ref=None):
+    """Dynamic spectra, Sec. 2 Eqs. (dynspec), (ref); Sec. 4.2.
+
+    S: (m, n) spectra, perturbation steps by rows.  ref: optional (n,)
+    reference spectrum; default the perturbation mean.  Returns (Y, r).
+    """
+    S = _f64(S)
+    m, n = S.shape
+    Y = np.empty((m, n))
+    r = np.empty(n)
+    rp = None
+    if ref is not None:
+        ref = _f64(ref)
+        assert ref.shape == (n,)
+        rp = _p(ref)
+    lib().oracle_dynamic(m, n, _p(S), n, rp, _p(Y), _p(r))
+    return Y, r
+
+
+def hilbert_noda(m):
+    """Hilbert-Noda matrix, Sec. 2 Eq. (HilbNoda)."""
+    N = np.empty((m, m))
+    lib().oracle_hilbert_noda(m, _p(N))
+    return N
+
+
+def noda_transform(Y):
+    """z = N y for every column, Sec. 2 Eq. (disHT)."""
+    Y = _f64(Y)
+    m, n = Y.shape
+    Z = np.empty((m, n))
+    lib().oracle_noda_transform(m, n, _p(Y), _p(Z))
+    return Z
+
+
+def corr_ht(Y1, Y2):
+    """Direct route on dynamic spectra; returns full (phi, psi)."""
+    Y1, Y2 = _f64(Y1), _f64(Y2)
+    m, n1 = Y1.shape
+    m2, n2 = Y2.shape
+    assert m == m2 and m >= 2
+    phi = np.empty((n1, n2))
+    psi = np.empty((n1, n2))
+    lib().oracle_corr_ht(m, n1, n2, _p(Y1), _p(Y2), _p(phi), _p(psi))
+    return phi, psi
+
+
+def corr_ht_entries(Y1, Y2, rows, cols):
+    """Selected entries (rows[t], cols[t]) of the direct route."""
+    Y1, Y2 = _f64(Y1), _f64(Y2)
+    m, n1 = Y1.shape
+    _, n2 = Y2.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    assert rows.shape == cols.shape
+    assert (rows >= 0).all() and (rows < n1).all() and (cols >= 0).all() and (cols < n2).all()
+    phi = np.empty(rows.shape[0])
+    psi = np.empty(rows.shape[0])
+    lib().oracle_corr_ht_entries(m, n1, n2, _p(Y1), _p(Y2), rows.shape[0], _lp(rows), _lp(cols),
+                                 _p(phi), _p(psi))
+    return phi, psi
+
+
+def dft(Y):
+    """m-point DFT along the perturbation axis, Sec. 2 Eq. (disFT)."""
+    Y = _f64(Y)
+    m, n = Y.shape
+    re = np.empty((m, n))
+    im = np.empty((m, n))
+    lib().oracle_dft(m, n, _p(Y), _p(re), _p(im))
+    return re + 1j * im
+
+
+def corr_ft_circular(Y1, Y2, cF):
+    """m-point Fourier route with Hermitian-complete half spectrum."""
+    Y1, Y2 = _f64(Y1), _f64(Y2)
+    m, n1 = Y1.shape
+    _, n2 = Y2.shape
+    phi = np.empty((n1, n2))
+    psi = np.empty((n1, n2))
+    lib().oracle_corr_ft_circular(m, n1, n2, _p(Y1), _p(Y2), float(cF), _p(phi), _p(psi))
+    return phi, psi
+
+
+def corr_ft_circular_entries(Y1, Y2, cF, rows, cols):
+    Y1, Y2 = _f64(Y1), _f64(Y2)
+    m, n1 = Y1.shape
+    _, n2 = Y2.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    assert (rows >= 0).all() and (rows < n1).all() and (cols >= 0).all() and (cols < n2).all()
+    phi = np.empty(rows.shape[0])
+    psi = np.empty(rows.shape[0])
+    lib().oracle_corr_ft_circular_entries(m, n1, n2, _p(Y1), _p(Y2), float(cF), rows.shape[0],
+                                          _lp(rows), _lp(cols), _p(phi), _p(psi))
+    return phi, psi
+
+
+def corr_ft_padded(Y1, Y2, L=None):
+    """Zero-padded L-point Fourier route (L >= 2m-1) reproducing the direct route."""
+    Y1, Y2 = _f64(Y1), _f64(Y2)
+    m, n1 = Y1.shape
+    _, n2 = Y2.shape
+    if L is None:
+        L = 2 * m
+    phi = np.empty((n1, n2))
+    psi = np.empty((n1, n2))
+    lib().oracle_corr_ft_padded(m, n1, n2, _p(Y1), _p(Y2), int(L), _p(phi), _p(psi))
+    return phi, psi
+
+
+# --------------------------------------------------------------------------
+# Whole calculation (the paper's corr2d(): reference, dynamic spectra, route)
+# --------------------------------------------------------------------------
+def norm_factor(m, norm="noda", norm_value=None):
+    """cF, the factor applied to the Hermitian-weighted Fourier sum."""
+    if norm == "noda":
+        return 1.0 / (m * (m - 1))
+    if norm == "paper":
+        return 1.0 / (math.pi * (m - 1))
+    if norm == "custom":
+        return float(norm_value)
+    raise ValueError(norm)
+
+
+def corr2d(S1, S2=None, ref1=None, ref2=None, hilbert="noda", norm="noda", norm_value=None):
+    """Full (phi, psi) for homocorrelation (S2 None) or heterocorrelation."""
+    Y1, _ = dynamic(S1, ref1)
+    Y2 = Y1 if S2 is None else dynamic(S2, ref2)[0]
+    m = Y1.shape[0]
+    cF = norm_factor(m, norm, norm_value)
+    if hilbert == "noda":
+        phi, psi = corr_ht(Y1, Y2)
+        f = cF * m * (m - 1)
+        if f != 1.0:
+            phi = phi * f
+            psi = psi * f
+        return phi, psi
+    if hilbert == "circular":
+        return corr_ft_circular(Y1, Y2, cF)
+    raise ValueError(hilbert)
+
+
+def corr2d_entries(S1, rows, cols, S2=None, ref1=None, ref2=None, hilbert="noda",
+                   norm="noda", norm_value=None):
+    """Selected entries of corr2d(); the dynamic spectra are formed in full."""
+    Y1, _ = dynamic(S1, ref1)
+    Y2 = Y1 if S2 is None else dynamic(S2, ref2)[0]
+    m = Y1.shape[0]
+    cF = norm_factor(m, norm, norm_value)
+    if hilbert == "noda":
+        phi, psi = corr_ht_entries(Y1, Y2, rows, cols)
+        f = cF * m * (m - 1)
+        if f != 1.0:
+            phi = phi * f
+            psi = psi * f
+        return phi, psi
+    if hilbert == "circular":
+        return corr_ft_circular_entries(Y1, Y2, cF, rows, cols)
+    raise ValueError(hilbert)
