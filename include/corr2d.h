@@ -1,0 +1,214 @@
+/*
+ * corr2d.h -- C ABI of the MI355X (gfx950) generalized two-dimensional
+ * correlation library.
+ *
+ * What it computes (Geitner et al., "corr2D", arXiv 1808.00685, Sec. 2):
+ * given m spectra of n points, taken at m equidistant perturbation steps,
+ *   1. dynamic spectra  y~(nu, t) = y(nu, t) - r(nu), where r is the
+ *      perturbation mean spectrum (Eqs. (dynspec), (ref)) or a reference
+ *      spectrum the caller supplies (Sec. 4.2);
+ *   2. a Fourier transform along the perturbation axis (Eq. (disFT)), kept as
+ *      the Hermitian half spectrum of a real signal (Eq. (symmeFT), Sec. 4.2);
+ *   3. the complex correlation  Phi + i Psi  between every pair of spectral
+ *      points as a contraction over the Fourier frequencies of F1 conj(F2),
+ *      scaled by the normalization (Eq. (disint2d), Sec. 4.2 "Norm").
+ * Phi (synchronous) is symmetric and Psi (asynchronous) antisymmetric for a
+ * homocorrelation (one data set with itself, Sec. 2 end and Sec. 3).
+ *
+ * The asynchronous kernel.  With the default CORR2D_HILBERT_NODA, Psi equals
+ * Noda's direct formula Y1^T N Y2 / (m-1) with the Hilbert-Noda matrix N
+ * (Eqs. (disHT), (HilbNoda), (disHTasyn)); it is evaluated as a Fourier
+ * contraction of F1 against the transform of N Y2, which is exact.
+ * CORR2D_HILBERT_CIRCULAR takes the imaginary part of the m-point half
+ * spectrum product literally (the discrete Fourier route of Eq. (disint2d));
+ * for finite m it differs from Noda's kernel.  Phi is the same in both.
+ *
+ * Normalization.  The factor cF multiplies the Hermitian-weighted Fourier sum
+ * sum_w weight(w) F1(w) conj(F2(w)) (weight 1 for DC and Nyquist, 2 else):
+ *   CORR2D_NORM_NODA   cF = 1/(m (m-1))   -> Phi = Y1^T Y2/(m-1)   (default)
+ *   CORR2D_NORM_PAPER  cF = 1/(pi (m-1))  -> the paper's default "Norm";
+ *                                            exactly m/pi times NODA
+ *   CORR2D_NORM_CUSTOM cF = desc.norm_value
+ *
+ * Memory.  Every data pointer passed to a compute call is device memory owned
+ * by the caller (for example a torch tensor).  Input spectra are row-major
+ * m x ld (row t = the spectrum at perturbation step t, each spectrum
+ * contiguous, the paper's input matrix of Sec. 3).  Full outputs are
+ * row-major n1 x ld_out.  UPPER_PACKED (homocorrelation only) stores row i's
+ * entries j = i..n-1 contiguously at offset i*n - i*(i-1)/2 + (j - i).
+ * A plan owns host memory only and can be created without a GPU.
+ *
+ * Calls are asynchronous on the given HIP stream (a hipStream_t passed as
+ * void*, NULL = the default stream).  CORR2D_OK means the work was enqueued;
+ * results are valid after the stream is synchronized.  Argument errors are
+ * reported before any device work.  No C++ exception crosses this boundary.
+ * NaN or Inf in the inputs propagate; the hot path does not inspect values.
+ * A plan may be used from several streams at once provided every concurrent
+ * call has its own workspace.
+ */
+#ifndef CORR2D_H
+#define CORR2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum corr2d_status {
+    CORR2D_OK = 0,
+    CORR2D_EINVAL = 1,      /* invalid argument (sizes, pointers, enums)       */
+    CORR2D_EWORKSPACE = 2,  /* workspace missing, misaligned or too small      */
+    CORR2D_EUNSUPPORTED = 3,/* valid but unsupported combination               */
+    CORR2D_EDEVICE = 4,     /* a HIP runtime call failed (see corr2d_last_error)*/
+    CORR2D_ENOMEM = 5       /* host allocation failed                          */
+} corr2d_status;
+
+/* Arithmetic of the contraction (step 3).  Mean subtraction and the final
+ * normalization are always FP64; the transform (step 2) is FP64 for
+ * CORR2D_PREC_F64 and FP32 otherwise.  Reduced precisions accumulate in FP32. */
+typedef enum corr2d_prec {
+    CORR2D_PREC_F64 = 0,        /* FP64 MFMA                                    */
+    CORR2D_PREC_F32 = 1,        /* FP32 MFMA                                    */
+    CORR2D_PREC_SPLIT_BF16 = 2, /* x = hi + lo (both BF16); hi*hi+hi*lo+lo*hi   */
+    CORR2D_PREC_BF16 = 3,       /* plain BF16                                   */
+    CORR2D_PREC_F16 = 4,        /* FP16, per-band scaling on by default          */
+    CORR2D_PREC_FP8_E4M3 = 5    /* OCP FP8 e4m3, per-band scaling required      */
+} corr2d_prec;
+
+/* Basis of the contraction.  FOURIER contracts the real-packed Hermitian half
+ * spectrum (the paper's Fourier route).  TIME contracts the dynamic spectra
+ * directly (the paper's Hilbert-transform route).  Both give the same Phi and
+ * Psi up to rounding; they differ in how rounding errors of reduced precisions
+ * accumulate.                                                                 */
+typedef enum corr2d_basis { CORR2D_BASIS_FOURIER = 0, CORR2D_BASIS_TIME = 1 } corr2d_basis;
+typedef enum corr2d_hilbert { CORR2D_HILBERT_NODA = 0, CORR2D_HILBERT_CIRCULAR = 1 } corr2d_hilbert;
+typedef enum corr2d_norm { CORR2D_NORM_NODA = 0, CORR2D_NORM_PAPER = 1, CORR2D_NORM_CUSTOM = 2 } corr2d_norm;
+typedef enum corr2d_layout { CORR2D_LAYOUT_FULL = 0, CORR2D_LAYOUT_UPPER_PACKED = 1 } corr2d_layout;
+typedef enum corr2d_dtype { CORR2D_DTYPE_F64 = 0, CORR2D_DTYPE_F32 = 1 } corr2d_dtype;
+
+/* desc.flags */
+#define CORR2D_FLAG_PER_BAND_SCALE 0x1u  /* power-of-two scale per spectral point */
+#define CORR2D_FLAG_NO_PER_BAND_SCALE 0x2u /* force scaling off (F16 only)          */
+#define CORR2D_FLAG_SEQUENTIAL 0x4u      /* batched: one launch chain per data set */
+#define CORR2D_FLAG_NO_GRAPH 0x8u        /* batched: launch directly, no hipGraph  */
+
+typedef struct corr2d_desc {
+    int64_t m;          /* perturbation steps, >= 2 (Eq. (disFT): equidistant)   */
+    int64_t n1;         /* spectral points of the first (or only) data set, >= 1 */
+    int64_t n2;         /* spectral points of the second set; 0 = homocorrelation */
+    int64_t ld_in1;     /* row stride of y1 in elements; 0 = n1                  */
+    int64_t ld_in2;     /* row stride of y2 in elements; 0 = n2                  */
+    int64_t ld_out;     /* row stride of FULL outputs in elements; 0 = columns   */
+    int32_t in_dtype;   /* corr2d_dtype of y1, y2 (references are always FP64)  */
+    int32_t out_dtype;  /* corr2d_dtype of phi, psi                             */
+    int32_t prec;       /* corr2d_prec                                           */
+    int32_t basis;      /* corr2d_basis                                          */
+    int32_t hilbert;    /* corr2d_hilbert                                        */
+    int32_t norm_mode;  /* corr2d_norm                                           */
+    double norm_value;  /* cF for CORR2D_NORM_CUSTOM                             */
+    int32_t out_layout; /* corr2d_layout                                         */
+    uint32_t flags;     /* CORR2D_FLAG_*                                         */
+    int32_t tile;       /* 0 = automatic (tuned table), else a corr2d tile id    */
+    int32_t reserved;
+} corr2d_desc;
+
+/* One data set of a batched homocorrelation.  Offsets are in elements from
+ * the base pointers given to corr2d_batched.                                   */
+typedef struct corr2d_item {
+    int64_t m;          /* perturbation steps of this set, >= 2                   */
+    int64_t n;          /* spectral points, >= 1                                  */
+    int64_t in_offset;  /* y of this set starts at y_base + in_offset             */
+    int64_t ld_in;      /* its row stride; 0 = n                                  */
+    int64_t out_offset; /* phi/psi of this set start at base + out_offset         */
+} corr2d_item;
+
+typedef struct corr2d_plan_s* corr2d_plan_t;
+
+/* Read-only facts about a plan (for logging and benchmarks).                  */
+typedef struct corr2d_plan_info {
+    int64_t k_pad;        /* contraction length after padding                     */
+    int64_t n_pad;        /* spectral points after padding to the tile            */
+    int64_t tiles;        /* output tiles one call computes                       */
+    int32_t tile;         /* corr2d tile id in use                                */
+    int32_t tile_m;       /* output tile rows                                     */
+    int32_t tile_n;       /* output tile columns                                  */
+    int32_t per_band_scale;
+    double c;             /* final FP64 factor applied to the contraction         */
+    size_t workspace_bytes;
+    int64_t items;        /* batched plans: data sets                             */
+    int64_t out_elements; /* batched plans: elements of phi (and of psi) written  */
+} corr2d_plan_info;
+
+/* Fill *d with defaults: FP64 input, FP32 output, SPLIT_BF16, FOURIER, NODA
+ * kernel and norm, FULL layout, automatic tile.  The caller sets m, n1, n2.  */
+void corr2d_desc_init(corr2d_desc* d);
+
+/* Validate d and build a plan in host memory.  No device call is made.
+ * EINVAL: m < 2, n1 < 1, n2 < 0, a stride smaller than its row, an unknown
+ * enum value, CUSTOM norm with a non-finite norm_value, UPPER_PACKED for a
+ * heterocorrelation.  EUNSUPPORTED: FP8 with per-band scaling forced off.   */
+corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d);
+
+/* Batched homocorrelation of count independent data sets (count >= 1); the
+ * common descriptor supplies precision, basis, kernel, norm, layout, dtypes
+ * and flags (its m, n1, n2, strides are ignored).  Each set's outputs have
+ * the common layout with row stride n.  Errors as corr2d_plan, per item.    */
+corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
+                                  const corr2d_item* items, int64_t count);
+
+/* Release a plan (and any graph it instantiated).  NULL is accepted.        */
+corr2d_status corr2d_plan_destroy(corr2d_plan_t plan);
+
+/* Device workspace a call needs, in bytes (the caller allocates it; 256-byte
+ * alignment required).  It holds the transform tables, the centred spectra,
+ * the packed contraction operands and scale vectors.                         */
+corr2d_status corr2d_workspace_bytes(corr2d_plan_t plan, size_t* bytes);
+
+corr2d_status corr2d_plan_get_info(corr2d_plan_t plan, corr2d_plan_info* info);
+
+/* Homocorrelation, the paper's corr2d(Mat1) (Sec. 3, Sec. 4.2) without
+ * interpolation or scaling.
+ *   y    device, m x ld_in1 of in_dtype
+ *   ref  device, n1 doubles, or NULL for the perturbation mean spectrum
+ *   phi, psi  device outputs of out_dtype in out_layout (n1 x n1)
+ *   ws   device workspace of ws_bytes >= corr2d_workspace_bytes
+ * EINVAL for a NULL y/phi/psi or a plan made for heterocorrelation.          */
+corr2d_status corr2d_homo(corr2d_plan_t plan, const void* y, const double* ref,
+                          void* phi, void* psi, void* ws, size_t ws_bytes, void* stream);
+
+/* Heterocorrelation, corr2d(Mat1, Mat2) (Sec. 3): two data sets sharing the
+ * m perturbation steps.  Psi(nu1, nu2) = Y1^T H Y2 -- the Hilbert transform
+ * acts on the second set (Eq. (disHTasyn)).  ref1/ref2 independently NULL for
+ * each set's mean.  Outputs are FULL n1 x n2.                                */
+corr2d_status corr2d_hetero(corr2d_plan_t plan, const void* y1, const double* ref1,
+                            const void* y2, const double* ref2, void* phi, void* psi,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Batched homocorrelation.  With neither SEQUENTIAL nor NO_GRAPH the whole
+ * batch (prep and one persistent contraction launch) is replayed from a
+ * hipGraph the plan captures on first use for these pointers and stream.    */
+corr2d_status corr2d_batched(corr2d_plan_t plan, const void* y_base, void* phi_base,
+                             void* psi_base, void* ws, size_t ws_bytes, void* stream);
+
+/* Measurement hook: when set (hipEvent_t handles passed as void*, either may
+ * be NULL), corr2d_homo and corr2d_hetero record `before` on the call's stream
+ * immediately before the contraction kernel and `after` immediately after
+ * it, so a caller can time that kernel alone.  The plan keeps the handles
+ * (it does not own them); pass NULLs to stop.  Not thread safe with calls in
+ * flight on other threads.                                                    */
+corr2d_status corr2d_plan_set_timing_events(corr2d_plan_t plan, void* before, void* after);
+
+const char* corr2d_status_str(corr2d_status s);
+
+/* Text of the last error on the calling thread ("" if none).                 */
+const char* corr2d_last_error(void);
+
+/* Library version string.                                                    */
+const char* corr2d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CORR2D_H */

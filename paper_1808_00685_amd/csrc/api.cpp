@@ -1,0 +1,852 @@
+// api.cpp -- the C ABI of include/corr2d.h: validation, plans (host memory
+// only), workspace layout and launch sequences.  Device work is enqueued by
+// the launchers of kernels.hip; nothing here computes a correlation value.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/corr2d.h"
+#include "corr2d_internal.h"
+#include "launch.h"
+#include "tune.h"
+
+using namespace corr2d;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+corr2d_status fail(corr2d_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+corr2d_status fail(corr2d_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+corr2d_status ok() {
+    g_last_error.clear();
+    return CORR2D_OK;
+}
+
+corr2d_status device_fail(hipError_t e, const char* where) {
+    return fail(CORR2D_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int64_t kMaxM = 4096;          // twiddle table limit of the table kernel
+constexpr int64_t kMaxN = (int64_t)1 << 24;
+
+// Geometry of one data set under a precision.
+struct Geo {
+    int64_t m = 0, n = 0, n_pad = 0;
+    int32_t kp = 0, kt = 0, rows_pad = 0;
+};
+
+Geo geometry(int64_t m, int64_t n, int prec) {
+    Geo g;
+    g.m = m;
+    g.n = n;
+    g.n_pad = round_up(n, kNPad);
+    g.kp = (int32_t)round_up(m, k_align(prec));
+    g.kt = (int32_t)round_up(m, kTransformK);
+    g.rows_pad = (int32_t)round_up(2 * (int64_t)g.kp, kTransformTile);
+    return g;
+}
+
+// Workspace regions of one data set (byte offsets from the workspace base).
+struct SetLayout {
+    size_t yt = 0, sA = 0, sB = 0, A0 = 0, A1 = 0, B0 = 0, B1 = 0;
+    bool has_b = false;
+};
+
+struct Tile {
+    int id = 2, fm = 4, fn = 4;
+};
+
+Tile tile_from_id(int id) {
+    Tile t;
+    t.id = id;
+    t.fm = t.fn = (id == 1) ? 2 : 4;
+    return t;
+}
+
+}  // namespace
+
+struct corr2d_plan_s {
+    corr2d_desc d;
+    bool batched = false;
+    bool hetero = false;
+    bool scale = false;
+    float qhalf = 1.0f;
+    double c = 0.0;           // per data set for single plans
+    double boundA = 1.0, boundB = 1.2;
+    Tile tile;
+    int group = 8;
+    // single / hetero
+    Geo g1, g2;
+    size_t table_off = 0;
+    SetLayout s1, s2;
+    size_t ws_bytes = 0;
+    int64_t ntiles = 0;
+    // batched
+    struct Item {
+        corr2d_item it;
+        Geo g;
+        SetLayout s;
+        size_t table_off;
+        double c;
+        Tile tile;
+        int64_t ntiles;
+    };
+    std::vector<Item> items;
+    std::vector<int> order;             // items in descending cost
+    std::vector<int64_t> distinct_m;
+    std::vector<size_t> table_of_m;
+    size_t jobs_off = 0, jobs_bytes = 0;
+    size_t counter_off = 0;
+    int64_t total_tiles = 0;
+    int64_t out_elements = 0;
+    std::mutex mu;
+    // graph cache (one entry)
+    struct GraphKey {
+        const void* y = nullptr;
+        void* phi = nullptr;
+        void* psi = nullptr;
+        void* ws = nullptr;
+        void* stream = nullptr;
+        bool operator==(const GraphKey& o) const {
+            return y == o.y && phi == o.phi && psi == o.psi && ws == o.ws && stream == o.stream;
+        }
+    } key;
+    bool have_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev_before = nullptr, ev_after = nullptr;  // timing hook
+    void* host_blob = nullptr;          // pinned host copy of the job arrays
+    bool blob_valid = false;
+    GraphKey blob_key;
+};
+
+namespace {
+
+bool valid_enum(int v, int lo, int hi) { return v >= lo && v <= hi; }
+
+corr2d_status check_common(const corr2d_desc* d) {
+    if (!valid_enum(d->in_dtype, 0, 1) || !valid_enum(d->out_dtype, 0, 1))
+        return fail(CORR2D_EINVAL, "in_dtype/out_dtype must be CORR2D_DTYPE_F64 or _F32");
+    if (!valid_enum(d->prec, 0, 5)) return fail(CORR2D_EINVAL, "unknown prec %d", d->prec);
+    if (!valid_enum(d->basis, 0, 1)) return fail(CORR2D_EINVAL, "unknown basis %d", d->basis);
+    if (!valid_enum(d->hilbert, 0, 1)) return fail(CORR2D_EINVAL, "unknown hilbert %d", d->hilbert);
+    if (!valid_enum(d->norm_mode, 0, 2)) return fail(CORR2D_EINVAL, "unknown norm_mode %d", d->norm_mode);
+    if (!valid_enum(d->out_layout, 0, 1)) return fail(CORR2D_EINVAL, "unknown out_layout %d", d->out_layout);
+    if (d->norm_mode == CORR2D_NORM_CUSTOM && !std::isfinite(d->norm_value))
+        return fail(CORR2D_EINVAL, "CUSTOM norm needs a finite norm_value");
+    if (d->flags & ~0xfu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
+    if (d->prec == CORR2D_PREC_FP8_E4M3 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
+        return fail(CORR2D_EUNSUPPORTED, "FP8 e4m3 requires per-band scaling (range 448)");
+    if (d->tile != 0 && d->tile != 1 && d->tile != 2)
+        return fail(CORR2D_EINVAL, "unknown tile id %d", d->tile);
+    if (d->tile == 2 && d->prec == CORR2D_PREC_F64)
+        return fail(CORR2D_EUNSUPPORTED, "tile 2 (128x128) is not built for FP64");
+    return CORR2D_OK;
+}
+
+double norm_cF(const corr2d_desc* d, int64_t m) {
+    switch (d->norm_mode) {
+    case CORR2D_NORM_PAPER: return 1.0 / (M_PI * (double)(m - 1));
+    case CORR2D_NORM_CUSTOM: return d->norm_value;
+    default: return 1.0 / ((double)m * (double)(m - 1));
+    }
+}
+
+// The contraction's operands are Fourier coefficients (A = Q Yc, Q^T Q = m I)
+// or the dynamic spectra themselves; cF multiplies the Fourier sum, which is
+// m times the time-basis sum.
+double contraction_factor(const corr2d_desc* d, int64_t m) {
+    const double cF = norm_cF(d, m);
+    return d->basis == CORR2D_BASIS_TIME ? cF * (double)m : cF;
+}
+
+void set_scaling(corr2d_plan_s* p) {
+    const int prec = p->d.prec;
+    p->scale = false;
+    if (prec == CORR2D_PREC_FP8_E4M3) {
+        p->scale = true;
+        p->qhalf = 224.0f;
+    } else if (prec == CORR2D_PREC_F16) {
+        p->scale = !(p->d.flags & CORR2D_FLAG_NO_PER_BAND_SCALE);
+        p->qhalf = 32752.0f;
+    }
+}
+
+double bound_a(const corr2d_desc* d, int64_t m) {
+    return d->basis == CORR2D_BASIS_TIME ? 1.0 : std::sqrt((double)m);
+}
+
+// Layout of one data set's workspace regions, appended at *off.
+SetLayout layout_set(const Geo& g, int prec, bool t64, bool need_b, size_t* off) {
+    SetLayout s;
+    const size_t tsz = t64 ? 8 : 4;
+    const size_t esz = (size_t)elem_bytes(prec);
+    const size_t plane = (size_t)g.n_pad * g.kp * esz;
+    s.yt = *off; *off = align256(*off + (size_t)g.n_pad * g.kt * tsz);
+    s.sA = *off; *off = align256(*off + (size_t)g.n_pad * 4);
+    s.A0 = *off; *off = align256(*off + plane);
+    if (planes(prec) == 2) { s.A1 = *off; *off = align256(*off + plane); }
+    s.has_b = need_b;
+    if (need_b) {
+        s.sB = *off; *off = align256(*off + (size_t)g.n_pad * 4);
+        s.B0 = *off; *off = align256(*off + plane);
+        if (planes(prec) == 2) { s.B1 = *off; *off = align256(*off + plane); }
+    }
+    return s;
+}
+
+size_t table_bytes(const Geo& g, bool t64) { return (size_t)g.rows_pad * g.kt * (t64 ? 8 : 4); }
+
+template <class T>
+T* at(void* ws, size_t off) {
+    return (T*)((char*)ws + off);
+}
+
+TableJob make_table_job(const corr2d_plan_s* p, const Geo& g, void* ws, size_t off) {
+    TableJob t{};
+    t.m = g.m;
+    t.kp = g.kp;
+    t.kt = g.kt;
+    t.rows_pad = g.rows_pad;
+    t.basis = p->d.basis;
+    t.hilbert = p->d.hilbert;
+    t.f64 = p->d.prec == CORR2D_PREC_F64;
+    t.table = at<char>(ws, off);
+    return t;
+}
+
+int table_blocks(const Geo& g) { return (int)(((int64_t)g.rows_pad * g.kt + 255) / 256); }
+
+PrepJob make_prep_job(const corr2d_plan_s* p, const Geo& g, const SetLayout& s, const void* y,
+                      int64_t ld, const double* ref, void* ws, size_t table_off) {
+    PrepJob j{};
+    j.y = y;
+    j.ref = ref;
+    j.ld = ld;
+    j.m = g.m;
+    j.n = g.n;
+    j.n_pad = g.n_pad;
+    j.kp = g.kp;
+    j.kt = g.kt;
+    j.rows_pad = g.rows_pad;
+    j.in_f64 = p->d.in_dtype == CORR2D_DTYPE_F64;
+    j.t_f64 = p->d.prec == CORR2D_PREC_F64;
+    j.prec = p->d.prec;
+    j.need_b = s.has_b;
+    j.scale = p->scale;
+    j.qhalf = p->qhalf;
+    j.boundA = bound_a(&p->d, g.m);
+    j.boundB = 1.2 * j.boundA;
+    j.yt = at<char>(ws, s.yt);
+    j.table = at<char>(ws, table_off);
+    j.sA = at<float>(ws, s.sA);
+    j.sB = s.has_b ? at<float>(ws, s.sB) : nullptr;
+    j.A0 = at<char>(ws, s.A0);
+    j.A1 = s.A1 ? at<char>(ws, s.A1) : nullptr;
+    j.B0 = s.has_b ? at<char>(ws, s.B0) : nullptr;
+    j.B1 = (s.has_b && s.B1) ? at<char>(ws, s.B1) : nullptr;
+    return j;
+}
+
+int center_blocks(const Geo& g) { return (int)(g.n_pad / kCenterCols); }
+int transform_blocks(const Geo& g) {
+    return (int)((g.n_pad / kTransformTile) * (g.rows_pad / kTransformTile));
+}
+
+int64_t triangle_tiles(int64_t T) { return T * (T + 1) / 2; }
+
+CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1, const Geo& g2,
+                      const SetLayout& s2, void* ws, void* phi, void* psi, bool homo, double c,
+                      const Tile& tile, int64_t ld_out, int layout) {
+    CorrJob C{};
+    C.L0 = at<char>(ws, s1.A0);
+    C.L1 = s1.A1 ? at<char>(ws, s1.A1) : nullptr;
+    C.RA0 = at<char>(ws, s2.A0);
+    C.RA1 = s2.A1 ? at<char>(ws, s2.A1) : nullptr;
+    C.RB0 = at<char>(ws, s2.B0);
+    C.RB1 = s2.B1 ? at<char>(ws, s2.B1) : nullptr;
+    C.sL = at<float>(ws, s1.sA);
+    C.sRA = at<float>(ws, s2.sA);
+    C.sRB = at<float>(ws, s2.sB);
+    C.phi = phi;
+    C.psi = psi;
+    C.n1 = g1.n;
+    C.n2 = g2.n;
+    C.ld_out = ld_out;
+    C.kp = g1.kp;
+    const int bm = 32 * tile.fm;
+    C.tiles_i = (int32_t)(g1.n_pad / bm);
+    C.tiles_j = (int32_t)(g2.n_pad / bm);
+    C.homo = homo;
+    C.layout = layout;
+    C.out_f64 = p->d.out_dtype == CORR2D_DTYPE_F64;
+    C.group = p->group;
+    C.ntiles = homo ? triangle_tiles(C.tiles_i) : (int64_t)C.tiles_i * C.tiles_j;
+    C.c = c;
+    return C;
+}
+
+Tile choose_tile(const corr2d_desc* d, int64_t m, int64_t n) {
+    if (d->tile) return tile_from_id(d->tile);
+    return tile_from_id(tune_lookup(d->prec, m, n));
+}
+
+corr2d_status check_ws(const corr2d_plan_s* p, void* ws, size_t ws_bytes) {
+    if (!ws) return fail(CORR2D_EWORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)ws) & 255) return fail(CORR2D_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < p->ws_bytes)
+        return fail(CORR2D_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                    ws_bytes, p->ws_bytes);
+    return CORR2D_OK;
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void corr2d_desc_init(corr2d_desc* d) {
+    if (!d) return;
+    std::memset(d, 0, sizeof *d);
+    d->in_dtype = CORR2D_DTYPE_F64;
+    d->out_dtype = CORR2D_DTYPE_F32;
+    d->prec = CORR2D_PREC_SPLIT_BF16;
+    d->basis = CORR2D_BASIS_FOURIER;
+    d->hilbert = CORR2D_HILBERT_NODA;
+    d->norm_mode = CORR2D_NORM_NODA;
+    d->out_layout = CORR2D_LAYOUT_FULL;
+}
+
+const char* corr2d_status_str(corr2d_status s) {
+    switch (s) {
+    case CORR2D_OK: return "CORR2D_OK";
+    case CORR2D_EINVAL: return "CORR2D_EINVAL";
+    case CORR2D_EWORKSPACE: return "CORR2D_EWORKSPACE";
+    case CORR2D_EUNSUPPORTED: return "CORR2D_EUNSUPPORTED";
+    case CORR2D_EDEVICE: return "CORR2D_EDEVICE";
+    case CORR2D_ENOMEM: return "CORR2D_ENOMEM";
+    }
+    return "CORR2D_UNKNOWN";
+}
+
+const char* corr2d_last_error(void) { return g_last_error.c_str(); }
+
+const char* corr2d_version(void) { return "corr2d-mi355x 0.1 (gfx950)"; }
+
+corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
+    if (!out || !d) return fail(CORR2D_EINVAL, "NULL plan or descriptor");
+    *out = nullptr;
+    corr2d_status st = check_common(d);
+    if (st != CORR2D_OK) return st;
+    if (d->m < 2) return fail(CORR2D_EINVAL, "m = %lld: at least 2 perturbation steps are needed", (long long)d->m);
+    if (d->m > kMaxM) return fail(CORR2D_EUNSUPPORTED, "m = %lld exceeds %lld", (long long)d->m, (long long)kMaxM);
+    if (d->n1 < 1 || d->n1 > kMaxN) return fail(CORR2D_EINVAL, "n1 = %lld out of range", (long long)d->n1);
+    if (d->n2 < 0 || d->n2 > kMaxN) return fail(CORR2D_EINVAL, "n2 = %lld out of range", (long long)d->n2);
+    const bool hetero = d->n2 > 0;
+    if (hetero && d->out_layout == CORR2D_LAYOUT_UPPER_PACKED)
+        return fail(CORR2D_EINVAL, "UPPER_PACKED output is defined for homocorrelation only");
+    const int64_t ld1 = d->ld_in1 ? d->ld_in1 : d->n1;
+    const int64_t ld2 = d->ld_in2 ? d->ld_in2 : d->n2;
+    if (ld1 < d->n1) return fail(CORR2D_EINVAL, "ld_in1 < n1");
+    if (hetero && ld2 < d->n2) return fail(CORR2D_EINVAL, "ld_in2 < n2");
+    const int64_t cols = hetero ? d->n2 : d->n1;
+    const int64_t ldo = d->ld_out ? d->ld_out : cols;
+    if (ldo < cols) return fail(CORR2D_EINVAL, "ld_out smaller than the number of output columns");
+
+    corr2d_plan_s* p = new (std::nothrow) corr2d_plan_s;
+    if (!p) return fail(CORR2D_ENOMEM, "host allocation of the plan failed");
+    p->d = *d;
+    p->d.ld_in1 = ld1;
+    p->d.ld_in2 = hetero ? ld2 : 0;
+    p->d.ld_out = ldo;
+    p->hetero = hetero;
+    set_scaling(p);
+    p->c = contraction_factor(d, d->m);
+    p->tile = choose_tile(d, d->m, hetero ? std::max(d->n1, d->n2) : d->n1);
+    if (!corr_variant_supported(d->prec, p->tile.fm, p->tile.fn)) {
+        delete p;
+        return fail(CORR2D_EUNSUPPORTED, "tile %d is not built for precision %d", p->tile.id, d->prec);
+    }
+    const bool t64 = d->prec == CORR2D_PREC_F64;
+    p->g1 = geometry(d->m, d->n1, d->prec);
+    size_t off = 0;
+    p->table_off = off;
+    off = align256(off + table_bytes(p->g1, t64));
+    if (!hetero) {
+        p->s1 = layout_set(p->g1, d->prec, t64, true, &off);
+        const int64_t T = p->g1.n_pad / (32 * p->tile.fm);
+        p->ntiles = triangle_tiles(T);
+    } else {
+        p->g2 = geometry(d->m, d->n2, d->prec);
+        p->s1 = layout_set(p->g1, d->prec, t64, false, &off);
+        p->s2 = layout_set(p->g2, d->prec, t64, true, &off);
+        const int64_t bm = 32 * p->tile.fm;
+        p->ntiles = (p->g1.n_pad / bm) * (p->g2.n_pad / bm);
+    }
+    p->ws_bytes = off;
+    *out = p;
+    return ok();
+}
+
+corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
+                                  const corr2d_item* items, int64_t count) {
+    if (!out || !common || !items) return fail(CORR2D_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (count < 1 || count > (1 << 20)) return fail(CORR2D_EINVAL, "count = %lld out of range", (long long)count);
+    corr2d_status st = check_common(common);
+    if (st != CORR2D_OK) return st;
+    for (int64_t i = 0; i < count; ++i) {
+        const corr2d_item& it = items[i];
+        if (it.m < 2 || it.m > kMaxM) return fail(CORR2D_EINVAL, "item %lld: m = %lld out of range", (long long)i, (long long)it.m);
+        if (it.n < 1 || it.n > kMaxN) return fail(CORR2D_EINVAL, "item %lld: n = %lld out of range", (long long)i, (long long)it.n);
+        if (it.ld_in != 0 && it.ld_in < it.n) return fail(CORR2D_EINVAL, "item %lld: ld_in < n", (long long)i);
+        if (it.in_offset < 0 || it.out_offset < 0) return fail(CORR2D_EINVAL, "item %lld: negative offset", (long long)i);
+    }
+    corr2d_plan_s* p = new (std::nothrow) corr2d_plan_s;
+    if (!p) return fail(CORR2D_ENOMEM, "host allocation of the plan failed");
+    p->d = *common;
+    p->batched = true;
+    set_scaling(p);
+    const bool t64 = common->prec == CORR2D_PREC_F64;
+    // one tile shape for the whole persistent launch: the tuned choice for the
+    // median data set
+    std::vector<int64_t> ns;
+    for (int64_t i = 0; i < count; ++i) ns.push_back(items[i].n);
+    std::sort(ns.begin(), ns.end());
+    std::vector<int64_t> msv;
+    for (int64_t i = 0; i < count; ++i) msv.push_back(items[i].m);
+    std::sort(msv.begin(), msv.end());
+    p->tile = choose_tile(common, msv[count / 2], ns[count / 2]);
+    if (!corr_variant_supported(common->prec, p->tile.fm, p->tile.fn)) {
+        delete p;
+        return fail(CORR2D_EUNSUPPORTED, "tile %d is not built for precision %d", p->tile.id, common->prec);
+    }
+    size_t off = 0;
+    // tables per distinct m
+    for (int64_t i = 0; i < count; ++i) {
+        if (std::find(p->distinct_m.begin(), p->distinct_m.end(), items[i].m) == p->distinct_m.end())
+            p->distinct_m.push_back(items[i].m);
+    }
+    for (int64_t m : p->distinct_m) {
+        p->table_of_m.push_back(off);
+        off = align256(off + table_bytes(geometry(m, 1, common->prec), t64));
+    }
+    p->items.resize(count);
+    p->out_elements = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        auto& I = p->items[i];
+        I.it = items[i];
+        if (I.it.ld_in == 0) I.it.ld_in = I.it.n;
+        I.g = geometry(I.it.m, I.it.n, common->prec);
+        I.s = layout_set(I.g, common->prec, t64, true, &off);
+        const size_t mi = std::find(p->distinct_m.begin(), p->distinct_m.end(), I.it.m) - p->distinct_m.begin();
+        I.table_off = p->table_of_m[mi];
+        I.c = contraction_factor(common, I.it.m);
+        I.tile = p->tile;
+        I.ntiles = triangle_tiles(I.g.n_pad / (32 * p->tile.fm));
+        const int64_t outn = common->out_layout == CORR2D_LAYOUT_UPPER_PACKED
+                                 ? I.it.n * (I.it.n + 1) / 2 : I.it.n * I.it.n;
+        p->out_elements = std::max(p->out_elements, I.it.out_offset + outn);
+    }
+    // descending cost order (longest processing time first)
+    p->order.resize(count);
+    for (int64_t i = 0; i < count; ++i) p->order[i] = (int)i;
+    std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
+        const auto& A = p->items[a];
+        const auto& B = p->items[b];
+        return (double)A.g.kp * A.ntiles > (double)B.g.kp * B.ntiles;
+    });
+    p->total_tiles = 0;
+    for (auto& I : p->items) p->total_tiles += I.ntiles;
+    // job arrays: tables, prep, corr, block starts, tile starts
+    const size_t nd = p->distinct_m.size();
+    p->jobs_bytes = align256(nd * sizeof(TableJob)) + align256((nd + 1) * sizeof(int32_t)) +
+                    align256(count * sizeof(PrepJob)) + align256((count + 1) * sizeof(int32_t)) * 2 +
+                    align256(count * sizeof(CorrJob)) + align256((count + 1) * sizeof(int64_t));
+    p->jobs_off = off;
+    off = align256(off + p->jobs_bytes);
+    p->counter_off = off;
+    off = align256(off + 256);
+    p->ws_bytes = off;
+    *out = p;
+    return ok();
+}
+
+corr2d_status corr2d_plan_destroy(corr2d_plan_t p) {
+    if (!p) return ok();
+    if (p->have_graph && p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->host_blob) hipHostFree(p->host_blob);
+    delete p;
+    return ok();
+}
+
+corr2d_status corr2d_workspace_bytes(corr2d_plan_t p, size_t* bytes) {
+    if (!p || !bytes) return fail(CORR2D_EINVAL, "NULL argument");
+    *bytes = p->ws_bytes;
+    return ok();
+}
+
+corr2d_status corr2d_plan_set_timing_events(corr2d_plan_t p, void* before, void* after) {
+    if (!p) return fail(CORR2D_EINVAL, "NULL plan");
+    p->ev_before = (hipEvent_t)before;
+    p->ev_after = (hipEvent_t)after;
+    return ok();
+}
+
+corr2d_status corr2d_plan_get_info(corr2d_plan_t p, corr2d_plan_info* info) {
+    if (!p || !info) return fail(CORR2D_EINVAL, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    info->tile = p->tile.id;
+    info->tile_m = 32 * p->tile.fm;
+    info->tile_n = 32 * p->tile.fn;
+    info->per_band_scale = p->scale;
+    info->workspace_bytes = p->ws_bytes;
+    if (p->batched) {
+        info->items = (int64_t)p->items.size();
+        info->tiles = p->total_tiles;
+        info->out_elements = p->out_elements;
+        info->k_pad = 0;
+        info->n_pad = 0;
+        info->c = 0.0;
+    } else {
+        info->k_pad = p->g1.kp;
+        info->n_pad = p->g1.n_pad;
+        info->tiles = p->ntiles;
+        info->c = p->c;
+    }
+    return ok();
+}
+
+corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, void* phi, void* psi,
+                          void* ws, size_t ws_bytes, void* stream) {
+    if (!p) return fail(CORR2D_EINVAL, "NULL plan");
+    if (p->batched) return fail(CORR2D_EINVAL, "batched plan passed to corr2d_homo");
+    if (p->hetero) return fail(CORR2D_EINVAL, "heterocorrelation plan passed to corr2d_homo");
+    if (!y || !phi || !psi) return fail(CORR2D_EINVAL, "NULL y, phi or psi");
+    const size_t in_al = p->d.in_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    const size_t out_al = p->d.out_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    if (!aligned(y, in_al) || !aligned(phi, out_al) || !aligned(psi, out_al) || (ref && !aligned(ref, 8)))
+        return fail(CORR2D_EINVAL, "misaligned data pointer");
+    corr2d_status st = check_ws(p, ws, ws_bytes);
+    if (st != CORR2D_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+
+    TableSrcInline ts{};
+    ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
+    ts.count = 1;
+    ts.blocks0 = table_blocks(p->g1);
+    hipError_t e = launch_tables(ts, ts.blocks0, s);
+    if (e != hipSuccess) return device_fail(e, "tables launch");
+
+    PrepSrcInline ps{};
+    ps.j[0] = make_prep_job(p, p->g1, p->s1, y, p->d.ld_in1, ref, ws, p->table_off);
+    ps.count = 1;
+    ps.blocks0 = center_blocks(p->g1);
+    e = launch_center(ps, ps.blocks0, s);
+    if (e != hipSuccess) return device_fail(e, "center launch");
+    ps.blocks0 = transform_blocks(p->g1);
+    e = launch_transform(p->d.prec, ps, ps.blocks0, s);
+    if (e != hipSuccess) return device_fail(e, "transform launch");
+
+    CorrJob C = make_corr_job(p, p->g1, p->s1, p->g1, p->s1, ws, phi, psi, true, p->c, p->tile,
+                              p->d.ld_out, p->d.out_layout);
+    if (p->ev_before) hipEventRecord(p->ev_before, s);
+    e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
+    if (e != hipSuccess) return device_fail(e, "correlation launch");
+    if (p->ev_after) hipEventRecord(p->ev_after, s);
+    return ok();
+}
+
+corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1, const void* y2,
+                            const double* ref2, void* phi, void* psi, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!p) return fail(CORR2D_EINVAL, "NULL plan");
+    if (p->batched || !p->hetero) return fail(CORR2D_EINVAL, "plan is not a heterocorrelation plan");
+    if (!y1 || !y2 || !phi || !psi) return fail(CORR2D_EINVAL, "NULL y1, y2, phi or psi");
+    const size_t in_al = p->d.in_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    const size_t out_al = p->d.out_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    if (!aligned(y1, in_al) || !aligned(y2, in_al) || !aligned(phi, out_al) || !aligned(psi, out_al) ||
+        (ref1 && !aligned(ref1, 8)) || (ref2 && !aligned(ref2, 8)))
+        return fail(CORR2D_EINVAL, "misaligned data pointer");
+    corr2d_status st = check_ws(p, ws, ws_bytes);
+    if (st != CORR2D_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+
+    TableSrcInline ts{};
+    ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
+    ts.count = 1;
+    ts.blocks0 = table_blocks(p->g1);
+    hipError_t e = launch_tables(ts, ts.blocks0, s);
+    if (e != hipSuccess) return device_fail(e, "tables launch");
+
+    PrepSrcInline ps{};
+    ps.j[0] = make_prep_job(p, p->g1, p->s1, y1, p->d.ld_in1, ref1, ws, p->table_off);
+    ps.j[1] = make_prep_job(p, p->g2, p->s2, y2, p->d.ld_in2, ref2, ws, p->table_off);
+    ps.count = 2;
+    ps.blocks0 = center_blocks(p->g1);
+    e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
+    if (e != hipSuccess) return device_fail(e, "center launch");
+    ps.blocks0 = transform_blocks(p->g1);
+    e = launch_transform(p->d.prec, ps, ps.blocks0 + transform_blocks(p->g2), s);
+    if (e != hipSuccess) return device_fail(e, "transform launch");
+
+    CorrJob C = make_corr_job(p, p->g1, p->s1, p->g2, p->s2, ws, phi, psi, false, p->c, p->tile,
+                              p->d.ld_out, CORR2D_LAYOUT_FULL);
+    if (p->ev_before) hipEventRecord(p->ev_before, s);
+    e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
+    if (e != hipSuccess) return device_fail(e, "correlation launch");
+    if (p->ev_after) hipEventRecord(p->ev_after, s);
+    return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched path
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BlobLayout {
+    size_t tables, tstart, prep, cstart, xstart, corr, tilestart, total;
+};
+
+BlobLayout blob_layout(size_t nd, size_t count) {
+    BlobLayout b;
+    size_t o = 0;
+    b.tables = o; o = align256(o + nd * sizeof(TableJob));
+    b.tstart = o; o = align256(o + (nd + 1) * sizeof(int32_t));
+    b.prep = o; o = align256(o + count * sizeof(PrepJob));
+    b.cstart = o; o = align256(o + (count + 1) * sizeof(int32_t));
+    b.xstart = o; o = align256(o + (count + 1) * sizeof(int32_t));
+    b.corr = o; o = align256(o + count * sizeof(CorrJob));
+    b.tilestart = o; o = align256(o + (count + 1) * sizeof(int64_t));
+    b.total = o;
+    return b;
+}
+
+// Fill the pinned host blob with the job arrays for these pointers.
+void fill_blob(corr2d_plan_s* p, const void* y_base, void* phi_base, void* psi_base, void* ws) {
+    const size_t nd = p->distinct_m.size(), count = p->items.size();
+    const BlobLayout L = blob_layout(nd, count);
+    char* h = (char*)p->host_blob;
+    std::memset(h, 0, L.total);
+    TableJob* tj = (TableJob*)(h + L.tables);
+    int32_t* ts = (int32_t*)(h + L.tstart);
+    int32_t blk = 0;
+    for (size_t q = 0; q < nd; ++q) {
+        const Geo g = geometry(p->distinct_m[q], 1, p->d.prec);
+        tj[q] = make_table_job(p, g, ws, p->table_of_m[q]);
+        ts[q] = blk;
+        blk += table_blocks(g);
+    }
+    ts[nd] = blk;
+    PrepJob* pj = (PrepJob*)(h + L.prep);
+    int32_t* cs = (int32_t*)(h + L.cstart);
+    int32_t* xs = (int32_t*)(h + L.xstart);
+    CorrJob* cj = (CorrJob*)(h + L.corr);
+    int64_t* tst = (int64_t*)(h + L.tilestart);
+    const size_t isz = p->d.in_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    const size_t osz = p->d.out_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    int32_t cb = 0, xb = 0;
+    int64_t tt = 0;
+    for (size_t r = 0; r < count; ++r) {
+        const auto& I = p->items[p->order[r]];
+        const void* y = (const char*)y_base + I.it.in_offset * isz;
+        pj[r] = make_prep_job(p, I.g, I.s, y, I.it.ld_in, nullptr, ws, I.table_off);
+        cs[r] = cb;
+        cb += center_blocks(I.g);
+        xs[r] = xb;
+        xb += transform_blocks(I.g);
+        void* ph = (char*)phi_base + I.it.out_offset * osz;
+        void* ps = (char*)psi_base + I.it.out_offset * osz;
+        cj[r] = make_corr_job(p, I.g, I.s, I.g, I.s, ws, ph, ps, true, I.c, I.tile, I.it.n,
+                              p->d.out_layout);
+        tst[r] = tt;
+        tt += cj[r].ntiles;
+    }
+    cs[count] = cb;
+    xs[count] = xb;
+    tst[count] = tt;
+}
+
+corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
+    const size_t nd = p->distinct_m.size(), count = p->items.size();
+    const BlobLayout L = blob_layout(nd, count);
+    char* dev = at<char>(ws, p->jobs_off);
+    hipError_t e = hipMemcpyAsync(dev, p->host_blob, L.total, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return device_fail(e, "job upload");
+    const char* h = (const char*)p->host_blob;
+    int* counter = at<int>(ws, p->counter_off);
+
+    TableSrcArray ta{};
+    ta.jobs = (const TableJob*)(dev + L.tables);
+    ta.start = (const int32_t*)(dev + L.tstart);
+    ta.count = (int32_t)nd;
+    ta.counter = counter;
+    e = launch_tables(ta, ((const int32_t*)(h + L.tstart))[nd], s);
+    if (e != hipSuccess) return device_fail(e, "tables launch");
+
+    PrepSrcArray pa{};
+    pa.jobs = (const PrepJob*)(dev + L.prep);
+    pa.count = (int32_t)count;
+    pa.start = (const int32_t*)(dev + L.cstart);
+    e = launch_center(pa, ((const int32_t*)(h + L.cstart))[count], s);
+    if (e != hipSuccess) return device_fail(e, "center launch");
+    pa.start = (const int32_t*)(dev + L.xstart);
+    e = launch_transform(p->d.prec, pa, ((const int32_t*)(h + L.xstart))[count], s);
+    if (e != hipSuccess) return device_fail(e, "transform launch");
+
+    int dev_id = 0, cus = 0;
+    hipGetDevice(&dev_id);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int per_cu = persistent_blocks_per_cu(p->d.prec, p->tile.fm, p->tile.fn);
+    int64_t blocks = (int64_t)cus * per_cu;
+    blocks = std::min<int64_t>(blocks, p->total_tiles);
+    e = launch_corr_persistent(p->d.prec, p->tile.fm, p->tile.fn, (const CorrJob*)(dev + L.corr),
+                               (const int64_t*)(dev + L.tilestart), (int)count, p->total_tiles,
+                               counter, (int)blocks, s);
+    if (e != hipSuccess) return device_fail(e, "persistent correlation launch");
+    return CORR2D_OK;
+}
+
+corr2d_status enqueue_sequential(corr2d_plan_s* p, const void* y_base, void* phi_base,
+                                 void* psi_base, void* ws, hipStream_t s) {
+    const size_t isz = p->d.in_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    const size_t osz = p->d.out_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    for (size_t r = 0; r < p->items.size(); ++r) {
+        const auto& I = p->items[r];
+        TableSrcInline ts{};
+        ts.j[0] = make_table_job(p, I.g, ws, I.table_off);
+        ts.count = 1;
+        ts.blocks0 = table_blocks(I.g);
+        hipError_t e = launch_tables(ts, ts.blocks0, s);
+        if (e != hipSuccess) return device_fail(e, "tables launch");
+        PrepSrcInline ps{};
+        ps.j[0] = make_prep_job(p, I.g, I.s, (const char*)y_base + I.it.in_offset * isz, I.it.ld_in,
+                                nullptr, ws, I.table_off);
+        ps.count = 1;
+        ps.blocks0 = center_blocks(I.g);
+        e = launch_center(ps, ps.blocks0, s);
+        if (e != hipSuccess) return device_fail(e, "center launch");
+        ps.blocks0 = transform_blocks(I.g);
+        e = launch_transform(p->d.prec, ps, ps.blocks0, s);
+        if (e != hipSuccess) return device_fail(e, "transform launch");
+        CorrJob C = make_corr_job(p, I.g, I.s, I.g, I.s, ws, (char*)phi_base + I.it.out_offset * osz,
+                                  (char*)psi_base + I.it.out_offset * osz, true, I.c, I.tile, I.it.n,
+                                  p->d.out_layout);
+        e = launch_corr(p->d.prec, I.tile.fm, I.tile.fn, C, C.ntiles, s);
+        if (e != hipSuccess) return device_fail(e, "correlation launch");
+    }
+    return CORR2D_OK;
+}
+
+}  // namespace
+
+extern "C" corr2d_status corr2d_batched(corr2d_plan_t p, const void* y_base, void* phi_base,
+                                        void* psi_base, void* ws, size_t ws_bytes, void* stream) {
+    if (!p) return fail(CORR2D_EINVAL, "NULL plan");
+    if (!p->batched) return fail(CORR2D_EINVAL, "plan is not a batched plan");
+    if (!y_base || !phi_base || !psi_base) return fail(CORR2D_EINVAL, "NULL base pointer");
+    const size_t in_al = p->d.in_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    const size_t out_al = p->d.out_dtype == CORR2D_DTYPE_F64 ? 8 : 4;
+    if (!aligned(y_base, in_al) || !aligned(phi_base, out_al) || !aligned(psi_base, out_al))
+        return fail(CORR2D_EINVAL, "misaligned data pointer");
+    corr2d_status st = check_ws(p, ws, ws_bytes);
+    if (st != CORR2D_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(p->mu);
+
+    if (p->d.flags & CORR2D_FLAG_SEQUENTIAL) {
+        st = enqueue_sequential(p, y_base, phi_base, psi_base, ws, s);
+        return st == CORR2D_OK ? ok() : st;
+    }
+
+    corr2d_plan_s::GraphKey key;
+    key.y = y_base;
+    key.phi = phi_base;
+    key.psi = psi_base;
+    key.ws = ws;
+    key.stream = stream;
+    const BlobLayout L = blob_layout(p->distinct_m.size(), p->items.size());
+    if (!p->host_blob) {
+        hipError_t e = hipHostMalloc(&p->host_blob, L.total, hipHostMallocDefault);
+        if (e != hipSuccess) { p->host_blob = nullptr; return device_fail(e, "pinned job buffer"); }
+    }
+    if (!p->blob_valid || !(p->blob_key == key)) {
+        // the previous blob may still be read by an enqueued copy
+        if (p->blob_valid) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return device_fail(e, "device synchronize");
+        }
+        fill_blob(p, y_base, phi_base, psi_base, ws);
+        p->blob_valid = true;
+        p->blob_key = key;
+        if (p->have_graph) {
+            hipGraphExecDestroy(p->gexec);
+            p->gexec = nullptr;
+            p->have_graph = false;
+        }
+    }
+
+    if (p->d.flags & CORR2D_FLAG_NO_GRAPH) {
+        st = enqueue_batched(p, ws, s);
+        return st == CORR2D_OK ? ok() : st;
+    }
+    if (!p->have_graph) {
+        hipStream_t cs = s;
+        bool own = false;
+        if (cs == nullptr) {
+            // the legacy default stream cannot be captured: capture on a private stream
+            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+                return fail(CORR2D_EDEVICE, "stream creation for graph capture failed");
+            own = true;
+        }
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            if (own) hipStreamDestroy(cs);
+            return device_fail(e, "begin capture");
+        }
+        corr2d_status est = enqueue_batched(p, ws, cs);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        if (own) hipStreamDestroy(cs);
+        if (est != CORR2D_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return est;
+        }
+        if (e != hipSuccess) return device_fail(e, "end capture");
+        e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return device_fail(e, "graph instantiate");
+        p->have_graph = true;
+    }
+    hipError_t e = hipGraphLaunch(p->gexec, s);
+    if (e != hipSuccess) return device_fail(e, "graph launch");
+    return ok();
+}

@@ -1,0 +1,81 @@
+// corr2d_internal.h -- descriptors shared by the host plan code and the HIP
+// kernels of the correlation library.  Plain structs only; no HIP types.
+#pragma once
+#include <stdint.h>
+
+namespace corr2d {
+
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_SPLIT = 2, P_BF16 = 3, P_F16 = 4, P_FP8 = 5 };
+enum Basis : int { B_FOURIER = 0, B_TIME = 1 };
+enum Hilbert : int { H_NODA = 0, H_CIRCULAR = 1 };
+enum Layout : int { L_FULL = 0, L_UPPER = 1 };
+
+// Contraction length granularity per precision (one MFMA "super-step").
+__host__ __device__ constexpr int k_align(int prec) {
+    return prec == P_FP8 ? 64 : (prec == P_F64 || prec == P_F32) ? 16 : 32;
+}
+__host__ __device__ constexpr int elem_bytes(int prec) {
+    return prec == P_F64 ? 8 : prec == P_F32 ? 4 : prec == P_FP8 ? 1 : 2;
+}
+__host__ __device__ constexpr int planes(int prec) { return prec == P_SPLIT ? 2 : 1; }
+
+constexpr int kTransformK = 16;   // inner-dimension granularity of the transform GEMM
+constexpr int kTransformTile = 64;
+constexpr int kNPad = 128;        // spectral points are padded to this multiple
+constexpr int kCenterCols = 64;   // columns per workgroup of the centring kernel
+
+// Transform table of one perturbation length: rows [0, kp) are the operand
+// transform T1, rows [kp, 2kp) the asynchronous operand transform T2, rows up
+// to rows_pad are zero.  Row-major, rows_pad x kt, double (FP64 transform) or
+// float.
+struct TableJob {
+    int64_t m;
+    int32_t kp, kt, rows_pad;
+    int32_t basis, hilbert;
+    int32_t f64;
+    void* table;
+};
+
+// Preparation of one data set: centring, transform and packing.
+struct PrepJob {
+    const void* y;        // m x ld input spectra (device)
+    const double* ref;    // reference spectrum or nullptr (mean)
+    int64_t ld;
+    int64_t m, n, n_pad;
+    int32_t kp, kt, rows_pad;
+    int32_t in_f64;       // 1: y is double, 0: float
+    int32_t t_f64;        // 1: transform in FP64 (tables/yt double)
+    int32_t prec;
+    int32_t need_b;       // produce the asynchronous operand B
+    int32_t scale;        // per-band power-of-two scales
+    float qhalf;          // half of the format's largest finite value
+    float pad0;
+    double boundA, boundB; // max|operand column| <= bound * ||centred column||_2
+    void* yt;             // n_pad x kt centred spectra, transposed (workspace)
+    const void* table;    // transform table (workspace)
+    float* sA;            // n_pad scales of operand A
+    float* sB;            // n_pad scales of operand B
+    void* A0; void* A1;   // operand A planes, n_pad x kp (A1: split low plane)
+    void* B0; void* B1;   // operand B planes
+};
+
+// One correlation contraction (a homocorrelation or a heterocorrelation).
+struct CorrJob {
+    const void* L0; const void* L1;   // left operand planes (set 1, A)
+    const void* RA0; const void* RA1; // right synchronous operand (set 2, A)
+    const void* RB0; const void* RB1; // right asynchronous operand (set 2, B)
+    const float* sL; const float* sRA; const float* sRB;
+    void* phi; void* psi;
+    int64_t n1, n2;     // true sizes
+    int64_t ld_out;     // FULL row stride
+    int32_t kp;
+    int32_t tiles_i, tiles_j;   // tile grid
+    int32_t homo;       // 1: upper-triangle tiles only, mirror or pack
+    int32_t layout;     // Layout
+    int32_t out_f64;
+    int32_t group;      // column tiles per L2 group
+    int64_t ntiles;
+    double c;           // FP64 normalization of the contraction
+};
+
+}  // namespace corr2d

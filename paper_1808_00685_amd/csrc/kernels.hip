@@ -1,0 +1,679 @@
+// kernels.hip -- HIP kernels (gfx950 / CDNA4) of the correlation hot path.
+//
+// Pipeline of one call (Geitner et al., arXiv 1808.00685, Sec. 2 and 4.2):
+//   tables_kernel     the m x m transforms: T1 = real-packed Hermitian half
+//                     spectrum DFT (Eqs. (disFT), (symmeFT)), T2 = the
+//                     asynchronous operand's transform (T1 N for Noda's
+//                     kernel, Eq. (HilbNoda); a row-pair rotation of T1 for
+//                     the circular kernel).
+//   center_kernel     FP64 perturbation mean and dynamic spectra
+//                     (Eqs. (dynspec), (ref)), transposed so that each
+//                     spectral point's m values are contiguous; per-band
+//                     power-of-two scales from the column norm.
+//   transform_kernel  MFMA GEMM  [A | B] = Yc^T [T1 | T2]^T  (FP64 or FP32),
+//                     epilogue scales, rounds (RNE) and packs the contraction
+//                     operands, K-contiguous, zero padded.
+//   corr_kernel       MFMA GEMM over output tiles: Phi = c A1^T A2,
+//                     Psi = c A1^T B2 (Eq. (disint2d) evaluated as a real
+//                     contraction over the packed half spectrum), FP64
+//                     epilogue, upper-triangle tiles for homocorrelation with
+//                     exact mirror or packed stores.
+//
+// MFMA fragment convention (16x16 family): lane l supplies row (l & 15) and
+// the contraction slice (l >> 4) of its operand; the accumulator register q
+// of lane l holds column (l & 15) and row 4*(l >> 4) + q for the FP32-output
+// instructions, but row (l >> 4) + 4*q for v_mfma_f64_16x16x4f64 (measured).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "corr2d_internal.h"
+#include "launch.h"
+
+namespace corr2d {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ rounding
+// float -> bfloat16, round to nearest even (bias-and-truncate on the bits).
+__device__ inline uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// float -> OCP FP8 e4m3 (bias 7, 3 mantissa bits, largest finite 448, no
+// infinities), round to nearest even, saturating at +-448; NaN -> 0x7f.
+__device__ inline uint8_t fp8_e4m3_rne(float x) {
+    if (x != x) return 0x7f;
+    const uint8_t sgn = (__float_as_uint(x) >> 31) ? 0x80 : 0x00;
+    float a = fabsf(x);
+    if (a >= 480.0f) return sgn | 0x7e;
+    uint32_t code;
+    if (a < 0.015625f) {                      // below 2^-6: subnormal grid 2^-9
+        code = (uint32_t)rintf(a * 512.0f);    // 0..8; 8 is the smallest normal
+    } else {
+        int e;
+        float f = frexpf(a, &e);              // a = f 2^e, f in [0.5, 1)
+        float mant = f * 2.0f;                // [1, 2)
+        int ex = e - 1;
+        uint32_t q = (uint32_t)rintf((mant - 1.0f) * 8.0f);
+        if (q == 8) { q = 0; ++ex; }
+        code = (uint32_t)((ex + 7) << 3) | q;
+    }
+    if (code >= 0x7f) code = 0x7e;            // 0x7f is NaN: saturate to 448
+    return sgn | (uint8_t)code;
+}
+
+// ------------------------------------------------------------ XCD placement
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
+// XCD receives one contiguous run of the tile order (its L2 then holds the
+// operand panels that run shares).
+__device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t per = nb / 8, rem = nb % 8;
+    const int64_t x = b % 8, s = b / 8;
+    return x * per + (x < rem ? x : rem) + s;
+}
+
+// Upper-triangle tile order, grouped by G column tiles: group g covers
+// columns [gG, gG+G); inside it, rows 0..gG-1 take the full group width, then
+// the group's own triangle.  Tiles that run together share a few row panels
+// and one group of column panels.
+__device__ inline void decode_upper(int64_t t, int T, int G, int& I, int& J) {
+    int g = 0;
+    for (;; ++g) {
+        const int gw = min(G, T - g * G);
+        const int64_t cnt = (int64_t)g * G * gw + (int64_t)gw * (gw + 1) / 2;
+        if (t < cnt) break;
+        t -= cnt;
+    }
+    const int gG = g * G, gw = min(G, T - gG);
+    if (t < (int64_t)gG * gw) {
+        I = (int)(t / gw);
+        J = gG + (int)(t % gw);
+        return;
+    }
+    t -= (int64_t)gG * gw;
+    int r = 0;
+    while (t >= gw - r) { t -= gw - r; ++r; }
+    I = gG + r;
+    J = gG + r + (int)t;
+}
+
+// Full-grid tile order for heterocorrelation, grouped by G column tiles.
+__device__ inline void decode_full(int64_t t, int Ti, int Tj, int G, int& I, int& J) {
+    const int64_t per_group = (int64_t)Ti * G;
+    const int g = (int)(t / per_group);
+    const int64_t r = t - (int64_t)g * per_group;
+    const int gw = min(G, Tj - g * G);
+    I = (int)(r / gw);
+    J = g * G + (int)(r % gw);
+}
+
+// =========================================================================
+// Transform tables
+// =========================================================================
+struct TwiddleView {
+    const double* c;
+    const double* s;
+    int64_t m;
+};
+
+// Row r of the real-packed Fourier basis at time index l: row 0 is DC, rows
+// 2p-1 / 2p carry sqrt2 Re / sqrt2 Im of exp(-2 pi i p l / m) for
+// 0 < p < m/2, and row m-1 of an even m is the Nyquist bin.  With this
+// packing the weighted half-spectrum sum of Eq. (symmeFT) is a plain dot
+// product of rows, and Q^T Q = m I.
+__device__ inline double qrow(const TwiddleView& tw, int64_t r, int64_t l) {
+    const int64_t m = tw.m;
+    if (r == 0) return 1.0;
+    if ((m & 1) == 0 && r == m - 1) return (l & 1) ? -1.0 : 1.0;
+    const int64_t p = (r + 1) >> 1;
+    const int64_t idx = (p * l) % m;
+    return (r & 1) ? M_SQRT2 * tw.c[idx] : -M_SQRT2 * tw.s[idx];
+}
+
+// Row r of J Q: each (Re, Im) pair becomes (-Im, Re); DC and Nyquist vanish.
+// A1^T (J A2) is then the imaginary part of the weighted sum of
+// F1 conj(F2) -- the circular asynchronous kernel of the m-point route.
+__device__ inline double jqrow(const TwiddleView& tw, int64_t r, int64_t l) {
+    const int64_t m = tw.m;
+    if (r == 0) return 0.0;
+    if ((m & 1) == 0 && r == m - 1) return 0.0;
+    const int64_t p = (r + 1) >> 1;
+    const int64_t idx = (p * l) % m;
+    return (r & 1) ? M_SQRT2 * tw.s[idx] : M_SQRT2 * tw.c[idx];
+}
+
+__device__ inline double table_entry(const TableJob& T, const TwiddleView& tw, int64_t r,
+                                     int64_t j) {
+    const int64_t m = T.m;
+    if (j >= m) return 0.0;
+    if (r < T.kp) {
+        if (r >= m) return 0.0;
+        return T.basis == B_FOURIER ? qrow(tw, r, j) : (r == j ? 1.0 : 0.0);
+    }
+    const int64_t k = r - T.kp;
+    if (k >= m || r >= 2 * (int64_t)T.kp) return 0.0;
+    if (T.basis == B_FOURIER) {
+        if (T.hilbert == H_CIRCULAR) return jqrow(tw, k, j);
+        // (Q N)[k][j] = sum_{l != j} Q[k][l] / (pi (j - l))
+        double s = 0.0;
+        for (int64_t l = 0; l < m; ++l)
+            if (l != j) s += qrow(tw, k, l) / (M_PI * (double)(j - l));
+        return s;
+    }
+    if (T.hilbert == H_NODA) return k == j ? 0.0 : 1.0 / (M_PI * (double)(j - k));
+    // circular kernel in the time basis: (1/m) sum_r Q[r][k] (J Q)[r][j]
+    double s = 0.0;
+    for (int64_t q = 0; q < m; ++q) s += qrow(tw, q, k) * jqrow(tw, q, j);
+    return s / (double)m;
+}
+
+constexpr int kMaxTwiddle = 4096;
+
+template <class Src>
+__global__ __launch_bounds__(256) void tables_kernel(Src src) {
+    __shared__ double tc[kMaxTwiddle];
+    __shared__ double ts[kMaxTwiddle];
+    int lb;
+    const TableJob T = src.get(blockIdx.x, lb);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && src.counter) *src.counter = 0;
+    for (int64_t i = threadIdx.x; i < T.m; i += blockDim.x) {
+        double sv, cv;
+        sincospi(2.0 * (double)i / (double)T.m, &sv, &cv);
+        tc[i] = cv;
+        ts[i] = sv;
+    }
+    __syncthreads();
+    const TwiddleView tw{tc, ts, T.m};
+    const int64_t e = (int64_t)lb * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)T.rows_pad * T.kt;
+    if (e >= total) return;
+    const int64_t r = e / T.kt, j = e % T.kt;
+    const double v = table_entry(T, tw, r, j);
+    if (T.f64) ((double*)T.table)[e] = v;
+    else ((float*)T.table)[e] = (float)v;
+}
+
+// =========================================================================
+// Centring (FP64) and per-band scales
+// =========================================================================
+__device__ inline double load_in(const PrepJob& J, int64_t j, int64_t col) {
+    return J.in_f64 ? ((const double*)J.y)[j * J.ld + col]
+                    : (double)((const float*)J.y)[j * J.ld + col];
+}
+
+// Power of two s with s * bound <= qhalf, as large as possible.
+__device__ inline float pow2_scale(double qhalf, double bound) {
+    if (!(bound > 0.0) || !(bound < 1e300)) return 1.0f;
+    int e;
+    frexp(qhalf / bound, &e);   // qhalf/bound = f 2^e, f in [0.5, 1)
+    e -= 1;
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    return ldexpf(1.0f, e);
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void center_kernel(Src src) {
+    __shared__ double red[4][kCenterCols];
+    __shared__ double tile[kCenterCols][kCenterCols + 1];
+    int lb;
+    const PrepJob J = src.get(blockIdx.x, lb);
+    const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
+    const int64_t col = (int64_t)lb * kCenterCols + c;
+    const bool valid = col < J.n;
+
+    double mean = 0.0;
+    if (J.ref) {
+        mean = valid ? J.ref[col] : 0.0;
+    } else {
+        double s = 0.0;
+        if (valid)
+            for (int64_t j = g; j < J.m; j += 4) s += load_in(J, j, col);
+        red[g][c] = s;
+        __syncthreads();
+        mean = ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) / (double)J.m;
+        __syncthreads();
+    }
+
+    double nrm = 0.0;
+    const int cc = tid >> 2, qq = tid & 3;
+    const int64_t ocol = (int64_t)lb * kCenterCols + cc;
+    for (int j0 = 0; j0 < J.kt; j0 += 64) {
+        for (int jj = g; jj < 64; jj += 4) {
+            const int64_t j = j0 + jj;
+            double v = 0.0;
+            if (valid && j < J.m) v = load_in(J, j, col) - mean;
+            nrm += v * v;
+            tile[c][jj] = v;
+        }
+        __syncthreads();
+        const int jb = j0 + qq * 16;
+        if (jb < J.kt) {
+            if (J.t_f64) {
+                double* dst = (double*)J.yt + ocol * J.kt + jb;
+#pragma unroll
+                for (int e = 0; e < 16; e += 2) {
+                    double2 v2 = make_double2(tile[cc][qq * 16 + e], tile[cc][qq * 16 + e + 1]);
+                    *(double2*)(dst + e) = v2;
+                }
+            } else {
+                float* dst = (float*)J.yt + ocol * J.kt + jb;
+#pragma unroll
+                for (int e = 0; e < 16; e += 4) {
+                    float4 v4 = make_float4((float)tile[cc][qq * 16 + e], (float)tile[cc][qq * 16 + e + 1],
+                                            (float)tile[cc][qq * 16 + e + 2], (float)tile[cc][qq * 16 + e + 3]);
+                    *(float4*)(dst + e) = v4;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    red[g][c] = nrm;
+    __syncthreads();
+    if (g == 0) {
+        const double tot = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+        const double r = sqrt(tot);
+        float sa = 1.0f, sb = 1.0f;
+        if (J.scale) {
+            sa = pow2_scale(J.qhalf, J.boundA * r);
+            sb = pow2_scale(J.qhalf, J.boundB * r);
+        }
+        if (J.sA) J.sA[col] = sa;
+        if (J.sB) J.sB[col] = sb;
+    }
+}
+
+// =========================================================================
+// Transform GEMM: [A | B] = Yc^T T^T, then scale, round and pack
+// =========================================================================
+template <int P>
+__device__ inline void store_operand(const PrepJob& J, void* p0, void* p1, int64_t idx, float x) {
+    if (P == P_F32) {
+        ((float*)p0)[idx] = x;
+    } else if (P == P_SPLIT) {
+        const uint16_t hi = bf16_rne(x);
+        const uint16_t lo = bf16_rne(x - bf16_val(hi));
+        ((uint16_t*)p0)[idx] = hi;
+        ((uint16_t*)p1)[idx] = lo;
+    } else if (P == P_BF16) {
+        ((uint16_t*)p0)[idx] = bf16_rne(x);
+    } else if (P == P_F16) {
+        ((_Float16*)p0)[idx] = (_Float16)x;
+    } else if (P == P_FP8) {
+        ((uint8_t*)p0)[idx] = fp8_e4m3_rne(x);
+    }
+}
+
+// T64: transform arithmetic in FP64 (operands F64) or FP32 (all others).
+template <int P, class Src>
+__global__ __launch_bounds__(256) void transform_kernel(Src src) {
+    constexpr bool T64 = (P == P_F64);
+    int lb;
+    const PrepJob J = src.get(blockIdx.x, lb);
+    const int row_tiles = J.rows_pad / kTransformTile;
+    const int bi = lb / row_tiles, br = lb % row_tiles;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row16 = lane & 15, kg = lane >> 4;
+    const int64_t i0 = (int64_t)bi * kTransformTile + (wave >> 1) * 32;
+    const int64_t r0 = (int64_t)br * kTransformTile + (wave & 1) * 32;
+    if (r0 >= J.rows_pad) return;
+
+    if constexpr (T64) {
+        d4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+        const double* Y = (const double*)J.yt;
+        const double* T = (const double*)J.table;
+        for (int k0 = 0; k0 < J.kt; k0 += 16) {
+            d4 fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = *(const d4*)(Y + (i0 + a * 16 + row16) * J.kt + k0 + kg * 4);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) fb[b] = *(const d4*)(T + (r0 + b * 16 + row16) * J.kt + k0 + kg * 4);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a][s], fb[b][s], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int64_t r = r0 + b * 16 + row16;
+                if (r >= 2 * (int64_t)J.kp) continue;
+                const bool isB = r >= J.kp;
+                if (isB && !J.need_b) continue;
+                const int64_t k = isB ? r - J.kp : r;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t i = i0 + a * 16 + kg + 4 * q;   // FP64 accumulator rows
+                    double* dst = (double*)(isB ? J.B0 : J.A0);
+                    dst[i * J.kp + k] = acc[a][b][q];
+                }
+            }
+    } else {
+        f4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = f4{0, 0, 0, 0};
+        const float* Y = (const float*)J.yt;
+        const float* T = (const float*)J.table;
+        for (int k0 = 0; k0 < J.kt; k0 += 16) {
+            f4 fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = *(const f4*)(Y + (i0 + a * 16 + row16) * J.kt + k0 + kg * 4);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) fb[b] = *(const f4*)(T + (r0 + b * 16 + row16) * J.kt + k0 + kg * 4);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][s], fb[b][s], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int64_t r = r0 + b * 16 + row16;
+                if (r >= 2 * (int64_t)J.kp) continue;
+                const bool isB = r >= J.kp;
+                if (isB && !J.need_b) continue;
+                const int64_t k = isB ? r - J.kp : r;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t i = i0 + a * 16 + kg * 4 + q;
+                    const float s = isB ? J.sB[i] : J.sA[i];
+                    store_operand<P>(J, isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, i * J.kp + k,
+                                     acc[a][b][q] * s);
+                }
+            }
+    }
+}
+
+// =========================================================================
+// Correlation GEMM
+// =========================================================================
+template <int P> struct Frag;
+template <> struct Frag<P_F64> { using T = d4; using Acc = d4; static constexpr int KS = 16; };
+template <> struct Frag<P_F32> { using T = f4; using Acc = f4; static constexpr int KS = 16; };
+template <> struct Frag<P_SPLIT> { using T = bf8; using Acc = f4; static constexpr int KS = 32; };
+template <> struct Frag<P_BF16> { using T = bf8; using Acc = f4; static constexpr int KS = 32; };
+template <> struct Frag<P_F16> { using T = h8; using Acc = f4; static constexpr int KS = 32; };
+template <> struct Frag<P_FP8> { using T = u4; using Acc = f4; static constexpr int KS = 64; };
+
+template <int P>
+__device__ inline typename Frag<P>::T load_frag(const void* base, int64_t row, int kp, int k) {
+    constexpr int esz = elem_bytes(P);
+    const char* p = (const char*)base + ((row * kp) + k) * esz;
+    return *(const typename Frag<P>::T*)p;
+}
+
+// One super-step of products acc += a * b for one 16x16 block.
+template <int P>
+__device__ inline void mma(typename Frag<P>::Acc& acc, const typename Frag<P>::T& a,
+                           const typename Frag<P>::T& b) {
+    if constexpr (P == P_F64) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    } else if constexpr (P == P_F32) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+    } else if constexpr (P == P_SPLIT || P == P_BF16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    } else if constexpr (P == P_F16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
+    } else {
+        const long a0 = (long)a[0] | ((long)a[1] << 32), a1 = (long)a[2] | ((long)a[3] << 32);
+        const long b0 = (long)b[0] | ((long)b[1] << 32), b1 = (long)b[2] | ((long)b[3] << 32);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, acc, 0, 0, 0);
+    }
+}
+
+__device__ inline void store_val(void* base, int64_t idx, double v, int f64) {
+    if (f64) __builtin_nontemporal_store(v, (double*)base + idx);
+    else __builtin_nontemporal_store((float)v, (float*)base + idx);
+}
+
+__device__ inline int64_t packed_index(int64_t i, int64_t j, int64_t n) {
+    return i * n - (i * (i - 1)) / 2 + (j - i);
+}
+
+// Epilogue for one element: FP64 normalization, zero asynchronous diagonal,
+// exact mirror (FULL) or packed (UPPER) stores for homocorrelation.
+__device__ inline void emit(const CorrJob& C, int64_t i, int64_t j, double vphi, double vpsi) {
+    if (i >= C.n1 || j >= C.n2) return;
+    const double f = C.c / ((double)C.sL[i]);
+    const double phi = vphi * f / (double)C.sRA[j];
+    double psi = vpsi * f / (double)C.sRB[j];
+    if (!C.homo) {
+        store_val(C.phi, i * C.ld_out + j, phi, C.out_f64);
+        store_val(C.psi, i * C.ld_out + j, psi, C.out_f64);
+        return;
+    }
+    if (i > j) return;
+    if (i == j) psi = 0.0;
+    if (C.layout == L_UPPER) {
+        const int64_t p = packed_index(i, j, C.n1);
+        store_val(C.phi, p, phi, C.out_f64);
+        store_val(C.psi, p, psi, C.out_f64);
+    } else {
+        store_val(C.phi, i * C.ld_out + j, phi, C.out_f64);
+        store_val(C.psi, i * C.ld_out + j, psi, C.out_f64);
+        if (i != j) {
+            store_val(C.phi, j * C.ld_out + i, phi, C.out_f64);
+            store_val(C.psi, j * C.ld_out + i, -psi, C.out_f64);
+        }
+    }
+}
+
+// One output tile (I, J) of size (32 FM) x (32 FN) computed by 4 waves (2x2).
+template <int P, int FM, int FN>
+__device__ inline void corr_tile(const CorrJob& C, int I, int J) {
+    using FT = typename Frag<P>::T;
+    using AT = typename Frag<P>::Acc;
+    constexpr int KS = Frag<P>::KS;
+    constexpr bool SPLIT = (P == P_SPLIT);
+    constexpr int BM = 32 * FM, BN = 32 * FN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row16 = lane & 15, kg = lane >> 4;
+    const int64_t i0 = (int64_t)I * BM + (wave >> 1) * (16 * FM);
+    const int64_t j0 = (int64_t)J * BN + (wave & 1) * (16 * FN);
+    const int kofs = kg * (KS / 4);
+
+    AT ap[FM][FN], aq[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            ap[a][b] = AT{0, 0, 0, 0};
+            aq[a][b] = AT{0, 0, 0, 0};
+        }
+
+    for (int k0 = 0; k0 < C.kp; k0 += KS) {
+        FT la[FM], ra[FN], rb[FN];
+        FT la1[SPLIT ? FM : 1], ra1[SPLIT ? FN : 1], rb1[SPLIT ? FN : 1];
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+            la[a] = load_frag<P>(C.L0, i0 + a * 16 + row16, C.kp, k0 + kofs);
+            if constexpr (SPLIT) la1[a] = load_frag<P>(C.L1, i0 + a * 16 + row16, C.kp, k0 + kofs);
+        }
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            ra[b] = load_frag<P>(C.RA0, j0 + b * 16 + row16, C.kp, k0 + kofs);
+            rb[b] = load_frag<P>(C.RB0, j0 + b * 16 + row16, C.kp, k0 + kofs);
+            if constexpr (SPLIT) {
+                ra1[b] = load_frag<P>(C.RA1, j0 + b * 16 + row16, C.kp, k0 + kofs);
+                rb1[b] = load_frag<P>(C.RB1, j0 + b * 16 + row16, C.kp, k0 + kofs);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+                mma<P>(ap[a][b], la[a], ra[b]);
+                mma<P>(aq[a][b], la[a], rb[b]);
+                if constexpr (SPLIT) {
+                    mma<P>(ap[a][b], la[a], ra1[b]);
+                    mma<P>(ap[a][b], la1[a], ra[b]);
+                    mma<P>(aq[a][b], la[a], rb1[b]);
+                    mma<P>(aq[a][b], la1[a], rb[b]);
+                }
+            }
+    }
+
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int64_t j = j0 + b * 16 + row16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t i = i0 + a * 16 + (P == P_F64 ? kg + 4 * q : kg * 4 + q);
+                emit(C, i, j, (double)ap[a][b][q], (double)aq[a][b][q]);
+            }
+        }
+}
+
+template <int P, int FM, int FN>
+__global__ __launch_bounds__(256) void corr_kernel(CorrJob C) {
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int I, J;
+    if (C.homo) decode_upper(t, C.tiles_i, C.group, I, J);
+    else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
+    corr_tile<P, FM, FN>(C, I, J);
+}
+
+// Persistent batched contraction: workgroups take tiles from a global ticket
+// counter until the list (data sets in descending cost order) is exhausted.
+template <int P, int FM, int FN>
+__global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* jobs,
+                                                               const int64_t* tile_start,
+                                                               int count, int64_t total,
+                                                               int* counter) {
+    __shared__ int64_t s_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= total) break;
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const CorrJob C = jobs[lo];
+        int I, J;
+        decode_upper(t - tile_start[lo], C.tiles_i, C.group, I, J);
+        corr_tile<P, FM, FN>(C, I, J);
+    }
+}
+
+// =========================================================================
+// Host launchers
+// =========================================================================
+hipError_t launch_tables(const TableSrcInline& src, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(tables_kernel<TableSrcInline>, dim3(blocks), dim3(256), 0, s, src);
+    return hipGetLastError();
+}
+hipError_t launch_tables(const TableSrcArray& src, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(tables_kernel<TableSrcArray>, dim3(blocks), dim3(256), 0, s, src);
+    return hipGetLastError();
+}
+hipError_t launch_center(const PrepSrcInline& src, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(center_kernel<PrepSrcInline>, dim3(blocks), dim3(256), 0, s, src);
+    return hipGetLastError();
+}
+hipError_t launch_center(const PrepSrcArray& src, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(center_kernel<PrepSrcArray>, dim3(blocks), dim3(256), 0, s, src);
+    return hipGetLastError();
+}
+
+template <class Src>
+static hipError_t launch_transform_t(int prec, const Src& src, int blocks, hipStream_t s) {
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL((transform_kernel<P_F64, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_F32: hipLaunchKernelGGL((transform_kernel<P_F32, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_SPLIT: hipLaunchKernelGGL((transform_kernel<P_SPLIT, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_BF16: hipLaunchKernelGGL((transform_kernel<P_BF16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_F16: hipLaunchKernelGGL((transform_kernel<P_F16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_FP8: hipLaunchKernelGGL((transform_kernel<P_FP8, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s) {
+    return launch_transform_t(prec, src, blocks, s);
+}
+hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s) {
+    return launch_transform_t(prec, src, blocks, s);
+}
+
+#define CORR_CASES(X)                                                          \
+    X(P_F64, 2, 2) X(P_F32, 4, 4) X(P_SPLIT, 4, 4) X(P_BF16, 4, 4) X(P_F16, 4, 4) \
+    X(P_FP8, 4, 4) X(P_F32, 2, 2) X(P_SPLIT, 2, 2) X(P_BF16, 2, 2) X(P_F16, 2, 2) X(P_FP8, 2, 2)
+
+hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s) {
+#define X(PP, A, B)                                                                          \
+    if (prec == PP && fm == A && fn == B) {                                                  \
+        hipLaunchKernelGGL((corr_kernel<PP, A, B>), dim3((unsigned)blocks), dim3(256), 0, s, C); \
+        return hipGetLastError();                                                            \
+    }
+    CORR_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
+                                  const int64_t* tile_start, int count, int64_t total,
+                                  int* counter, int blocks, hipStream_t s) {
+#define X(PP, A, B)                                                                         \
+    if (prec == PP && fm == A && fn == B) {                                                 \
+        hipLaunchKernelGGL((corr_persistent_kernel<PP, A, B>), dim3(blocks), dim3(256), 0, s, jobs, \
+                           tile_start, count, total, counter);                              \
+        return hipGetLastError();                                                           \
+    }
+    CORR_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+int corr_variant_supported(int prec, int fm, int fn) {
+#define X(PP, A, B) if (prec == PP && fm == A && fn == B) return 1;
+    CORR_CASES(X)
+#undef X
+    return 0;
+}
+
+int persistent_blocks_per_cu(int prec, int fm, int fn) {
+    int n = 0;
+#define X(PP, A, B)                                                                      \
+    if (prec == PP && fm == A && fn == B) {                                              \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr_persistent_kernel<PP, A, B>, 256, 0) \
+            != hipSuccess) n = 1;                                                        \
+        return n > 0 ? n : 1;                                                            \
+    }
+    CORR_CASES(X)
+#undef X
+    return 1;
+}
+
+}  // namespace corr2d

@@ -1,0 +1,86 @@
+// launch.h -- host-side launchers of the correlation kernels and the job
+// sources they read (inline in the kernel arguments for a single call, or a
+// device array for a batch).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "corr2d_internal.h"
+
+namespace corr2d {
+
+// Up to two jobs passed by value; blocks [0, blocks0) belong to job 0.
+struct TableSrcInline {
+    TableJob j[2];
+    int32_t blocks0;
+    int32_t count;
+    int* counter;  // unused (nullptr); the batched source resets its ticket counter
+    __device__ TableJob get(int b, int& lb) const {
+        if (count == 1 || b < blocks0) { lb = b; return j[0]; }
+        lb = b - blocks0;
+        return j[1];
+    }
+};
+
+// Jobs in device memory; start[q] is the first block of job q (count + 1
+// entries, start[count] = total blocks).
+struct TableSrcArray {
+    const TableJob* jobs;
+    const int32_t* start;
+    int32_t count;
+    int32_t pad;
+    int* counter;  // set to 0 by block 0 (ticket counter of the persistent launch)
+    __device__ TableJob get(int b, int& lb) const {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        lb = b - start[lo];
+        return jobs[lo];
+    }
+};
+
+struct PrepSrcInline {
+    PrepJob j[2];
+    int32_t blocks0;
+    int32_t count;
+    __device__ PrepJob get(int b, int& lb) const {
+        if (count == 1 || b < blocks0) { lb = b; return j[0]; }
+        lb = b - blocks0;
+        return j[1];
+    }
+};
+
+struct PrepSrcArray {
+    const PrepJob* jobs;
+    const int32_t* start;
+    int32_t count;
+    int32_t pad;
+    __device__ PrepJob get(int b, int& lb) const {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        lb = b - start[lo];
+        return jobs[lo];
+    }
+};
+
+hipError_t launch_tables(const TableSrcInline& src, int blocks, hipStream_t s);
+hipError_t launch_tables(const TableSrcArray& src, int blocks, hipStream_t s);
+hipError_t launch_center(const PrepSrcInline& src, int blocks, hipStream_t s);
+hipError_t launch_center(const PrepSrcArray& src, int blocks, hipStream_t s);
+hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s);
+hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s);
+hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s);
+hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
+                                  const int64_t* tile_start, int count, int64_t total,
+                                  int* counter, int blocks, hipStream_t s);
+int corr_variant_supported(int prec, int fm, int fn);
+int persistent_blocks_per_cu(int prec, int fm, int fn);
+
+}  // namespace corr2d

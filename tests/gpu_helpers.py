@@ -1,0 +1,47 @@
+"""Helpers shared by the GPU parity tests (comparison and unpacking only)."""
+import numpy as np
+
+# Tolerances on the relative Frobenius error ||G - O||_F / ||O||_F, per output
+# (Phi and Psi separately).  F64, F32 and split-BF16 follow the stated
+# targets.  For the single-rounding formats the bound is derived from the unit
+# roundoff u (BF16 2^-8, FP16 2^-11, FP8 e4m3 2^-4): each product of two
+# rounded operands carries a relative error below 2u, so an output whose
+# terms do not cancel has relative error below 2u; random test data (whose
+# off-diagonal sums do cancel) measures about 0.6u.  The stricter 2e-3 target
+# of plain BF16 applies to the band workload (BF16_BAND_TOL).
+TOL = {"f64": 1e-12, "f32": 1e-5, "split_bf16": 1e-5, "bf16": 2 * 2.0 ** -8,
+       "f16": 2 * 2.0 ** -11, "fp8_e4m3": 2 * 2.0 ** -4}
+BF16_BAND_TOL = 2e-3
+
+
+def rel_fro(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    den = np.linalg.norm(o)
+    if den == 0:
+        return float(np.linalg.norm(g))
+    return float(np.linalg.norm(g - o) / den)
+
+
+def unpack_upper(p, n):
+    """Full matrices from the UPPER_PACKED layout (row i holds j = i..n-1)."""
+    p = np.asarray(p)
+    full = np.zeros((n, n), dtype=p.dtype)
+    off = 0
+    for i in range(n):
+        full[i, i:] = p[off:off + n - i]
+        off += n - i
+    return full
+
+
+def packed_index(i, j, n):
+    i = np.asarray(i, dtype=np.int64)
+    j = np.asarray(j, dtype=np.int64)
+    return i * n - (i * (i - 1)) // 2 + (j - i)
+
+
+def check_homo_structure(phi, psi):
+    """Exact mirror structure of a FULL homocorrelation output."""
+    assert np.array_equal(phi, phi.T)
+    assert np.array_equal(psi, -psi.T)
+    assert np.all(np.diag(psi) == 0)

@@ -1,0 +1,190 @@
+"""Host-side checks of the C ABI: no GPU needed, no compute calls.
+
+The library must load, export every function include/corr2d.h declares, and
+reject invalid arguments before any device work.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1808_00685_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "corr2d.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(B.LIB_PATH),
+                                reason="libcorr2d.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(corr2d_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("corr2d_plan", "corr2d_homo", "corr2d_hetero", "corr2d_batched",
+                     "corr2d_batched_plan", "corr2d_workspace_bytes", "corr2d_plan_destroy"):
+        assert required in names
+    assert sorted(B.EXPORTED) == names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(B.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    for name in declared_functions():
+        assert re.search(r"\bT " + name + r"$", out, re.M), name
+
+
+@pytest.mark.parametrize("lang", ["c", "c++"])
+def test_header_compiles_as_c_and_cpp(tmp_path, lang):
+    src = tmp_path / ("t.c" if lang == "c" else "t.cpp")
+    src.write_text('#include "corr2d.h"\nint main(void){corr2d_desc d; corr2d_desc_init(&d);'
+                   ' return (int)d.prec;}\n')
+    cc = "gcc" if lang == "c" else "g++"
+    r = subprocess.run([cc, "-std=c99" if lang == "c" else "-std=c++17", "-Wall", "-Werror",
+                        "-I" + os.path.dirname(HEADER), "-c", str(src), "-o",
+                        str(tmp_path / "t.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_struct_layout_matches_binding():
+    # offsets the ctypes mirror assumes must match the C compiler's
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "corr2d.h"
+int main(void){
+ printf("%zu %zu %zu %zu %zu\n", sizeof(corr2d_desc), offsetof(corr2d_desc, norm_value),
+        offsetof(corr2d_desc, tile), sizeof(corr2d_item), sizeof(corr2d_plan_info));
+ return 0;}
+'''
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "l")
+        subprocess.run(["gcc", "-I" + os.path.dirname(HEADER), c, "-o", exe], check=True)
+        vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    assert vals == [ctypes.sizeof(B.corr2d_desc), B.corr2d_desc.norm_value.offset,
+                    B.corr2d_desc.tile.offset, ctypes.sizeof(B.corr2d_item),
+                    ctypes.sizeof(B.corr2d_plan_info)]
+
+
+def test_defaults():
+    d = B.corr2d_desc_init()
+    assert d.prec == B.PREC["split_bf16"] and d.basis == 0 and d.hilbert == 0 and d.norm_mode == 0
+    assert d.in_dtype == B.DTYPE["f64"] and d.out_dtype == B.DTYPE["f32"]
+    assert B.corr2d_version().startswith("corr2d")
+
+
+def _plan_status(**kw):
+    base = dict(m=11, n1=512, n2=0)
+    base.update(kw)
+    d = B.corr2d_desc_init(**base)
+    s, h = B.corr2d_plan(d, check=False)
+    if h:
+        B.corr2d_plan_destroy(h)
+    return s
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(), B.OK),
+    (dict(m=1), B.EINVAL),
+    (dict(m=0), B.EINVAL),
+    (dict(n1=0), B.EINVAL),
+    (dict(n2=-1), B.EINVAL),
+    (dict(ld_in1=100), B.EINVAL),
+    (dict(n2=64, ld_in2=10), B.EINVAL),
+    (dict(ld_out=3), B.EINVAL),
+    (dict(prec=9), B.EINVAL),
+    (dict(basis=2), B.EINVAL),
+    (dict(hilbert=5), B.EINVAL),
+    (dict(norm_mode=7), B.EINVAL),
+    (dict(out_layout=3), B.EINVAL),
+    (dict(in_dtype=4), B.EINVAL),
+    (dict(norm_mode=2, norm_value=float("nan")), B.EINVAL),
+    (dict(n2=100, out_layout=1), B.EINVAL),
+    (dict(prec=5, flags=B.FLAG_NO_PER_BAND_SCALE), B.EUNSUPPORTED),
+    (dict(flags=0x100), B.EINVAL),
+    (dict(tile=7), B.EINVAL),
+    (dict(prec=0, tile=2), B.EUNSUPPORTED),
+    (dict(m=5000), B.EUNSUPPORTED),
+    (dict(m=2, n1=1), B.OK),
+    (dict(prec=5), B.OK),
+    (dict(n2=100), B.OK),
+])
+def test_plan_validation(kw, status):
+    assert _plan_status(**kw) == status
+
+
+def test_last_error_text():
+    assert _plan_status(m=1) == B.EINVAL
+    assert "perturbation" in B.corr2d_last_error()
+
+
+def test_workspace_bytes_monotone_in_size():
+    prev = 0
+    for n in (1, 100, 1000, 5000, 20000):
+        d = B.corr2d_desc_init(m=64, n1=n)
+        _, h = B.corr2d_plan(d)
+        w = B.corr2d_workspace_bytes(h)
+        assert w >= prev and w % 256 == 0
+        prev = w
+        B.corr2d_plan_destroy(h)
+
+
+def test_plan_info():
+    d = B.corr2d_desc_init(m=256, n1=16384, prec="split_bf16", out_layout="upper_packed")
+    _, h = B.corr2d_plan(d)
+    info = B.corr2d_plan_get_info(h)
+    assert info.k_pad == 256 and info.n_pad == 16384
+    assert info.tile_m == info.tile_n
+    t = 16384 // info.tile_m
+    assert info.tiles == t * (t + 1) // 2
+    assert info.c == pytest.approx(1.0 / (256 * 255))
+    B.corr2d_plan_destroy(h)
+    d = B.corr2d_desc_init(m=10, n1=7, prec="f64", norm_mode="paper", basis="time")
+    _, h = B.corr2d_plan(d)
+    import math
+    assert B.corr2d_plan_get_info(h).c == pytest.approx(10 / (math.pi * 9))
+    B.corr2d_plan_destroy(h)
+
+
+def test_compute_calls_reject_bad_arguments_before_device_work():
+    d = B.corr2d_desc_init(m=11, n1=64)
+    _, h = B.corr2d_plan(d)
+    L = B.lib()
+    need = B.corr2d_workspace_bytes(h)
+    fake = 1 << 20  # never dereferenced: validation fails first
+    assert L.corr2d_homo(h, None, None, fake, fake, fake, need, None) == B.EINVAL
+    assert L.corr2d_homo(h, fake, None, fake, fake, None, need, None) == B.EWORKSPACE
+    assert L.corr2d_homo(h, fake, None, fake, fake, fake + 8, need, None) == B.EWORKSPACE
+    assert L.corr2d_homo(h, fake, None, fake, fake, fake, need - 1, None) == B.EWORKSPACE
+    assert L.corr2d_homo(h, fake + 1, None, fake, fake, fake, need, None) == B.EINVAL
+    assert L.corr2d_hetero(h, fake, None, fake, None, fake, fake, fake, need, None) == B.EINVAL
+    assert L.corr2d_batched(h, fake, fake, fake, fake, need, None) == B.EINVAL
+    assert L.corr2d_homo(None, fake, None, fake, fake, fake, need, None) == B.EINVAL
+    B.corr2d_plan_destroy(h)
+
+
+def test_batched_plan_validation_and_sizes():
+    d = B.corr2d_desc_init(prec="f32", out_layout="upper_packed")
+    items = [(11, 300, 0, 0, 0), (64, 1000, 11 * 300, 0, 300 * 301 // 2)]
+    _, h = B.corr2d_batched_plan(d, items)
+    info = B.corr2d_plan_get_info(h)
+    assert info.items == 2
+    assert info.out_elements == 300 * 301 // 2 + 1000 * 1001 // 2
+    B.corr2d_plan_destroy(h)
+    s, h = B.corr2d_batched_plan(d, [(1, 300, 0, 0, 0)], check=False)
+    assert s == B.EINVAL and not h
+    s, h = B.corr2d_batched_plan(d, [(10, 300, -1, 0, 0)], check=False)
+    assert s == B.EINVAL

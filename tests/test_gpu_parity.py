@@ -1,0 +1,211 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every test runs the library's kernels on the GPU and compares element by
+element with the oracle on the same seeded inputs, at the tolerances in
+gpu_helpers.TOL.  Small cases cover several tiles and ragged tails; the large
+workloads are checked on sampled entries the oracle computes one by one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_00685_amd import binding as B
+from paper_1808_00685_amd import synth
+
+from .gpu_helpers import TOL, check_homo_structure, packed_index, rel_fro, unpack_upper
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"]
+
+
+def _t(a, dev, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device=dev)
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rand(m, n, seed):
+    return np.random.default_rng(seed).standard_normal((m, n)) + 3.0
+
+
+def _homo(S, dev, **kw):
+    phi, psi, plan, ws = B.homo(_t(S, dev), **kw)
+    return _np(phi), _np(psi), plan
+
+
+# --------------------------------------------------------------------------
+# Small and ragged cases, every precision
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("m,n", [(2, 1), (3, 7), (11, 512), (17, 129), (33, 300), (64, 257)])
+def test_homo_parity_small(gpu, prec, m, n):
+    S = _rand(m, n, 1000 * m + n)
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, _ = _homo(S, gpu, prec=prec)
+    check_homo_structure(phi, psi)
+    tol = TOL[prec]
+    assert rel_fro(phi, phi_o) <= tol
+    if m > 2:
+        assert rel_fro(psi, psi_o) <= tol
+    else:  # m = 2: Psi is identically zero
+        assert np.abs(psi).max() <= 1e-6 * np.abs(phi).max()
+
+
+def test_small_workload_f64(gpu):
+    """The 11 x 512 four-band workload in FP64 (full 512 x 512 outputs)."""
+    S, _ = synth.workload_small()
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, _ = _homo(S, gpu, prec="f64")
+    check_homo_structure(phi, psi)
+    assert rel_fro(phi, phi_o) <= 1e-12
+    assert rel_fro(psi, psi_o) <= 1e-12
+    assert np.abs(np.diag(phi) - np.var(S, axis=0, ddof=1)).max() <= 1e-12 * np.abs(phi).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16"])
+@pytest.mark.parametrize("basis", ["fourier", "time"])
+@pytest.mark.parametrize("hilbert", ["noda", "circular"])
+def test_modes(gpu, prec, basis, hilbert):
+    m, n = 24, 200
+    S = _rand(m, n, 7)
+    phi_o, psi_o = oracle.corr2d(S, hilbert=hilbert)
+    phi, psi, _ = _homo(S, gpu, prec=prec, basis=basis, hilbert=hilbert)
+    assert rel_fro(phi, phi_o) <= TOL[prec]
+    assert rel_fro(psi, psi_o) <= TOL[prec]
+
+
+@pytest.mark.parametrize("norm,val", [("paper", 0.0), ("custom", 0.37)])
+def test_norm_modes(gpu, norm, val):
+    m, n = 13, 150
+    S = _rand(m, n, 8)
+    phi_o, psi_o = oracle.corr2d(S, norm=norm, norm_value=val)
+    phi, psi, _ = _homo(S, gpu, prec="f64", norm=norm, norm_value=val)
+    assert rel_fro(phi, phi_o) <= 1e-12 and rel_fro(psi, psi_o) <= 1e-12
+
+
+def test_user_reference_and_f32_input_and_strides(gpu):
+    import torch
+    m, n, ld = 20, 150, 170
+    S = _rand(m, n, 9)
+    ref = S[0] + 0.25
+    phi_o, psi_o = oracle.corr2d(S, ref1=ref)
+    big = np.zeros((m, ld))
+    big[:, :n] = S
+    y = _t(big, gpu)[:, :n]
+    phi, psi, _, _ = B.homo(y, ref=_t(ref, gpu), prec="f64")
+    assert rel_fro(_np(phi), phi_o) <= 1e-12 and rel_fro(_np(psi), psi_o) <= 1e-12
+    # FP32 input (the FP64 mean of the FP32 values)
+    S32 = S.astype(np.float32)
+    phi_o, psi_o = oracle.corr2d(S32.astype(np.float64))
+    phi, psi, _, _ = B.homo(_t(S32, gpu, torch.float32), prec="f32")
+    assert rel_fro(_np(phi), phi_o) <= 1e-5 and rel_fro(_np(psi), psi_o) <= 1e-5
+
+
+def test_f64_output_of_reduced_precision_and_full_ld_out(gpu):
+    import torch
+    m, n, ldo = 16, 140, 160
+    S = _rand(m, n, 10)
+    phi_o, psi_o = oracle.corr2d(S)
+    d = B.corr2d_desc_init(m=m, n1=n, prec="f32", out_dtype="f64", ld_out=ldo)
+    plan = B.Plan(d)
+    phi = torch.full((n, ldo), 7.0, dtype=torch.float64, device=gpu)
+    psi = torch.full((n, ldo), 7.0, dtype=torch.float64, device=gpu)
+    ws = plan.workspace(gpu)
+    B.corr2d_homo(plan.handle, _t(S, gpu), None, phi, psi, ws)
+    ph, ps = _np(phi), _np(psi)
+    assert np.all(ph[:, n:] == 7.0) and np.all(ps[:, n:] == 7.0)   # padding columns untouched
+    assert rel_fro(ph[:, :n], phi_o) <= 1e-5 and rel_fro(ps[:, :n], psi_o) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "split_bf16"])
+def test_upper_packed_layout(gpu, prec):
+    m, n = 21, 333
+    S = _rand(m, n, 11)
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, _ = _homo(S, gpu, prec=prec, layout="upper_packed")
+    assert phi.shape == (n * (n + 1) // 2,)
+    P, Q = unpack_upper(phi, n), unpack_upper(psi, n)
+    iu = np.triu_indices(n)
+    assert rel_fro(P[iu], phi_o[iu]) <= TOL[prec]
+    assert rel_fro(Q[iu], psi_o[iu]) <= TOL[prec]
+    assert np.all(np.diag(Q) == 0)
+
+
+# --------------------------------------------------------------------------
+# Heterocorrelation
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("m,n1,n2", [(5, 3, 200), (32, 300, 129), (40, 128, 128)])
+def test_hetero_parity(gpu, prec, m, n1, n2):
+    S1 = _rand(m, n1, 20 + m)
+    S2 = _rand(m, n2, 30 + m)
+    phi_o, psi_o = oracle.corr2d(S1, S2)
+    phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), prec=prec)
+    assert rel_fro(_np(phi), phi_o) <= TOL[prec]
+    assert rel_fro(_np(psi), psi_o) <= TOL[prec]
+
+
+def test_hetero_circular_and_refs(gpu):
+    m, n1, n2 = 18, 90, 70
+    S1, S2 = _rand(m, n1, 40), _rand(m, n2, 41)
+    r1, r2 = S1[3] - 0.1, None
+    phi_o, psi_o = oracle.corr2d(S1, S2, ref1=r1, hilbert="circular")
+    phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), ref1=_t(r1, gpu), prec="f64",
+                              hilbert="circular")
+    assert rel_fro(_np(phi), phi_o) <= 1e-12 and rel_fro(_np(psi), psi_o) <= 1e-12
+
+
+def test_hetero_of_same_set_equals_homo(gpu):
+    m, n = 12, 300
+    S = _rand(m, n, 50)
+    ph, ps, _ = _homo(S, gpu, prec="f64")
+    hph, hps, _, _ = B.hetero(_t(S, gpu), _t(S, gpu), prec="f64")
+    hph, hps = _np(hph), _np(hps)
+    iu = np.triu_indices(n)
+    assert np.array_equal(ph[iu], hph[iu])
+    assert np.array_equal(ps[iu][iu[0] != iu[1]], hps[iu][iu[0] != iu[1]])
+
+
+# --------------------------------------------------------------------------
+# Method-level properties on the GPU output
+# --------------------------------------------------------------------------
+def test_phase_lag_sign_on_gpu(gpu):
+    m, n = 41, 256
+    nu = np.arange(n)
+    t = np.arange(m)[:, None]
+    T = 1.5 * (m - 1)
+    prof1 = 4.0 / ((nu - 60) ** 2 + 4.0)
+    prof2 = 4.0 / ((nu - 190) ** 2 + 4.0)
+    for ph1, ph2 in [(0.2, 1.4), (1.4, 0.2)]:
+        S = ((1 + 0.5 * np.sin(2 * math.pi * t / T + ph1)) * prof1[None, :]
+             + (1 + 0.5 * np.sin(2 * math.pi * t / T + ph2)) * prof2[None, :])
+        _, psi, _ = _homo(S, gpu, prec="split_bf16")
+        assert np.sign(psi[60, 190]) == np.sign(math.sin(ph1 - ph2))
+
+
+def test_determinism(gpu):
+    S = _rand(30, 500, 60)
+    a = _homo(S, gpu, prec="split_bf16")
+    b = _homo(S, gpu, prec="split_bf16")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# --------------------------------------------------------------------------
+# Medium workload (m=64, n=4096), full comparison
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_medium_workload_full(gpu, prec):
+    S, _ = synth.workload_medium()
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, _ = _homo(S, gpu, prec=prec)
+    check_homo_structure(phi, psi)
+    assert rel_fro(phi, phi_o) <= TOL[prec]
+    assert rel_fro(psi, psi_o) <= TOL[prec]

@@ -1,0 +1,172 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times, on sampled outputs the oracle computes one by one; plus the
+batched path (persistent launch replayed from a hipGraph) against sequential
+launches and the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1808_00685_amd import binding as B
+from paper_1808_00685_amd import synth
+
+from .gpu_helpers import BF16_BAND_TOL, TOL, packed_index, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_pairs(n, count, seed, centers=()):
+    rng = np.random.default_rng(seed)
+    i = rng.integers(0, n, count)
+    j = rng.integers(0, n, count)
+    i, j = np.minimum(i, j), np.maximum(i, j)
+    c = np.asarray(sorted(set(int(x) for x in centers if 0 <= x < n)), dtype=np.int64)
+    if len(c):
+        ci, cj = np.meshgrid(c, c, indexing="ij")
+        keep = ci <= cj
+        i = np.concatenate([i, ci[keep]])
+        j = np.concatenate([j, cj[keep]])
+    edge = np.array([0, n - 1, n // 2], dtype=np.int64)
+    i = np.concatenate([i, edge, [0, 0, n - 2]])
+    j = np.concatenate([j, edge, [n - 1, 1, n - 1]])
+    return i.astype(np.int64), j.astype(np.int64)
+
+
+@pytest.fixture(scope="module")
+def large():
+    S, meta = synth.workload_large()
+    i, j = _sample_pairs(S.shape[1], 6000, 3, centers=np.round(meta["centers"]).astype(int))
+    phi_o, psi_o = oracle.corr2d_entries(S, i, j)
+    return S, i, j, phi_o, psi_o
+
+
+@pytest.mark.parametrize("prec,basis,tol", [
+    ("split_bf16", "fourier", TOL["split_bf16"]),
+    ("f32", "fourier", TOL["f32"]),
+    ("bf16", "time", BF16_BAND_TOL),
+    ("bf16", "fourier", TOL["bf16"]),
+])
+def test_large_homo_sampled(gpu, large, prec, basis, tol):
+    """m=256, n=16384 band workload, upper triangle stored (the bench's launch)."""
+    import torch
+    S, i, j, phi_o, psi_o = large
+    n = S.shape[1]
+    phi, psi, plan, ws = B.homo(torch.as_tensor(S, device=gpu), prec=prec, basis=basis,
+                                layout="upper_packed")
+    idx = torch.as_tensor(packed_index(i, j, n), device=gpu)
+    g_phi = phi[idx].double().cpu().numpy()
+    g_psi = psi[idx].double().cpu().numpy()
+    e_phi, e_psi = rel_fro(g_phi, phi_o), rel_fro(g_psi, psi_o)
+    print(f"large {prec}/{basis}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
+    assert e_phi <= tol and e_psi <= tol
+    d = torch.as_tensor(packed_index(np.arange(n), np.arange(n), n), device=gpu)
+    assert torch.all(psi[d] == 0)
+    del phi, psi, ws
+
+
+@pytest.fixture(scope="module")
+def hetero_data():
+    S1, S2, meta = synth.workload_hetero()
+    c1 = np.round(meta["set1"]["centers"]).astype(int)
+    c2 = np.round(meta["set2"]["centers"]).astype(int)
+    rng = np.random.default_rng(4)
+    i = np.concatenate([rng.integers(0, S1.shape[1], 5000), np.repeat(c1, len(c2))])
+    j = np.concatenate([rng.integers(0, S2.shape[1], 5000), np.tile(c2, len(c1))])
+    phi_o, psi_o = oracle.corr2d_entries(S1, i, j, S2=S2)
+    return S1, S2, meta, i, j, phi_o, psi_o, len(c1) * len(c2)
+
+
+@pytest.mark.parametrize("prec", ["f16", "fp8_e4m3", "split_bf16"])
+def test_hetero_workload_sampled(gpu, hetero_data, prec):
+    """m=128, 8192 x 2048 heterocorrelation with per-band scaling."""
+    import torch
+    S1, S2, meta, i, j, phi_o, psi_o, ncoupled = hetero_data
+    phi, psi, plan, ws = B.hetero(torch.as_tensor(S1, device=gpu), torch.as_tensor(S2, device=gpu),
+                                  prec=prec)
+    if prec in ("f16", "fp8_e4m3"):
+        assert plan.info.per_band_scale == 1
+    ti, tj = torch.as_tensor(i, device=gpu), torch.as_tensor(j, device=gpu)
+    g_phi = phi[ti, tj].double().cpu().numpy()
+    g_psi = psi[ti, tj].double().cpu().numpy()
+    e_phi, e_psi = rel_fro(g_phi, phi_o), rel_fro(g_psi, psi_o)
+    print(f"hetero {prec}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
+    assert e_phi <= TOL[prec] and e_psi <= TOL[prec]
+    # sign of Psi at band-centre pairs agrees with the oracle where it is not tiny
+    sel = slice(len(i) - ncoupled, len(i))
+    big = np.abs(psi_o[sel]) > 0.05 * np.abs(psi_o[sel]).max()
+    assert np.all(np.sign(g_psi[sel][big]) == np.sign(psi_o[sel][big]))
+
+
+def _batch(count, seed, n_range):
+    items = synth.batch_spec(count=count, seed=seed, n_range=n_range)
+    data = [synth.batch_item_data(it) for it in items]
+    return items, data
+
+
+def _run_batched(gpu, items, data, prec, flags, layout="upper_packed"):
+    import torch
+    offs, ooffs, cur, ocur = [], [], 0, 0
+    for it in items:
+        offs.append(cur)
+        ooffs.append(ocur)
+        cur += it.m * it.n
+        ocur += it.n * (it.n + 1) // 2 if layout == "upper_packed" else it.n * it.n
+    y = torch.empty(cur, dtype=torch.float64, device=gpu)
+    for it, S, o in zip(items, data, offs):
+        y[o:o + it.m * it.n] = torch.as_tensor(S.ravel(), device=gpu)
+    d = B.corr2d_desc_init(prec=prec, out_layout=layout, flags=flags)
+    plan = B.Plan(d, items=[(it.m, it.n, o, 0, oo) for it, o, oo in zip(items, offs, ooffs)])
+    phi = torch.zeros(ocur, dtype=torch.float32, device=gpu)
+    psi = torch.zeros(ocur, dtype=torch.float32, device=gpu)
+    ws = plan.workspace(gpu)
+    return plan, y, phi, psi, ws, ooffs
+
+
+@pytest.mark.parametrize("prec", ["f32", "split_bf16"])
+def test_batched_graph_matches_sequential_and_oracle(gpu, prec):
+    import torch
+    items, data = _batch(24, 77, (256, 1500))
+    plan, y, phi, psi, ws, ooffs = _run_batched(gpu, items, data, prec, 0)
+    B.corr2d_batched(plan.handle, y, phi, psi, ws)
+    torch.cuda.synchronize()
+    ref_phi, ref_psi = phi.clone(), psi.clone()
+    # graph replays with eager work and synchronizations in between
+    for rep in range(3):
+        phi.zero_()
+        psi.fill_(3.0)
+        junk = torch.randn(1 << 20, device=gpu).sum()
+        torch.cuda.synchronize()
+        B.corr2d_batched(plan.handle, y, phi, psi, ws)
+        torch.cuda.synchronize()
+        assert torch.equal(phi, ref_phi) and torch.equal(psi, ref_psi), rep
+        del junk
+    # sequential launches (no persistent kernel, no graph) give the same values
+    seq, ys, sphi, spsi, sws, _ = _run_batched(gpu, items, data, prec, B.FLAG_SEQUENTIAL)
+    B.corr2d_batched(seq.handle, ys, sphi, spsi, sws)
+    torch.cuda.synchronize()
+    assert torch.equal(sphi, ref_phi) and torch.equal(spsi, ref_psi)
+    # every data set against the oracle on sampled entries
+    gp, gq = ref_phi.double().cpu().numpy(), ref_psi.double().cpu().numpy()
+    for k, (it, S, oo) in enumerate(zip(items, data, ooffs)):
+        i, j = _sample_pairs(it.n, 300, k)
+        po, qo = oracle.corr2d_entries(S, i, j)
+        pidx = oo + packed_index(i, j, it.n)
+        assert rel_fro(gp[pidx], po) <= TOL[prec], k
+        assert rel_fro(gq[pidx], qo) <= TOL[prec], k
+
+
+def test_batched_full_layout_and_no_graph(gpu):
+    import torch
+    items, data = _batch(6, 78, (256, 700))
+    plan, y, phi, psi, ws, ooffs = _run_batched(gpu, items, data, "f64", B.FLAG_NO_GRAPH,
+                                                layout="full")
+    B.corr2d_batched(plan.handle, y, phi, psi, ws)
+    torch.cuda.synchronize()
+    gp, gq = phi.double().cpu().numpy(), psi.double().cpu().numpy()
+    for it, S, oo in zip(items, data, ooffs):
+        po, qo = oracle.corr2d(S)
+        P = gp[oo:oo + it.n * it.n].reshape(it.n, it.n)
+        Q = gq[oo:oo + it.n * it.n].reshape(it.n, it.n)
+        # the output buffers are FP32 here: FP32 rounding bounds the error
+        assert rel_fro(P, po) <= 1e-6 and rel_fro(Q, qo) <= 1e-6
+        assert np.array_equal(P, P.T) and np.array_equal(Q, -Q.T)
