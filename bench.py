@@ -142,11 +142,16 @@ def cpu_baseline(oracle, S, target_s):
     """The oracle's direct route on a bounded sample of output rows."""
     Y, _ = oracle.dynamic(S)
     m, n = Y.shape
-    rows = 32
-    t0 = time.perf_counter()
-    oracle.corr_ht(Y[:, :rows], Y)
-    dt = time.perf_counter() - t0
-    rows = int(min(n, max(32, rows * target_s / max(dt, 1e-3))))
+    # two short runs separate the per-row cost from the fixed cost (the
+    # Hilbert-Noda transform of all columns), then one run of ~target_s
+    times = {}
+    for r in (32, 128):
+        t0 = time.perf_counter()
+        oracle.corr_ht(Y[:, :r], Y)
+        times[r] = time.perf_counter() - t0
+    per_row = max((times[128] - times[32]) / 96.0, 1e-6)
+    fixed = max(times[32] - 32 * per_row, 0.0)
+    rows = int(min(n, max(128, (target_s - fixed) / per_row)))
     t0 = time.perf_counter()
     oracle.corr_ht(Y[:, :rows], Y)
     dt = time.perf_counter() - t0

@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/corr2d.h"
+#include "corr2d.h"
 #include "corr2d_internal.h"
 #include "launch.h"
 #include "tune.h"
@@ -162,6 +162,8 @@ corr2d_status check_common(const corr2d_desc* d) {
         return fail(CORR2D_EINVAL, "unknown tile id %d", d->tile);
     if (d->tile == 2 && d->prec == CORR2D_PREC_F64)
         return fail(CORR2D_EUNSUPPORTED, "tile 2 (128x128) is not built for FP64");
+    if (d->tile == 1 && blocked_layout(d->prec))
+        return fail(CORR2D_EUNSUPPORTED, "tile 1 (64x64) is not built for the 16-bit formats");
     return CORR2D_OK;
 }
 
@@ -302,6 +304,7 @@ CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1
     C.layout = layout;
     C.out_f64 = p->d.out_dtype == CORR2D_DTYPE_F64;
     C.group = p->group;
+    C.scaled = p->scale;
     C.ntiles = homo ? triangle_tiles(C.tiles_i) : (int64_t)C.tiles_i * C.tiles_j;
     C.c = c;
     return C;

@@ -10,9 +10,31 @@ enum Basis : int { B_FOURIER = 0, B_TIME = 1 };
 enum Hilbert : int { H_NODA = 0, H_CIRCULAR = 1 };
 enum Layout : int { L_FULL = 0, L_UPPER = 1 };
 
-// Contraction length granularity per precision (one MFMA "super-step").
+// 16-bit formats use the LDS-staged contraction kernel and the K-blocked
+// operand layout (see blocked_index); the others the register-direct kernel
+// and the row layout [i][kp].
+__host__ __device__ constexpr bool blocked_layout(int prec) {
+    return prec == P_SPLIT || prec == P_BF16 || prec == P_F16;
+}
+
+// Contraction length granularity per precision.
 __host__ __device__ constexpr int k_align(int prec) {
-    return prec == P_FP8 ? 64 : (prec == P_F64 || prec == P_F32) ? 16 : 32;
+    return prec == P_FP8 ? 64 : 16;
+}
+
+// Panel-blocked operand layout of the 16-bit formats.  Rows are grouped in
+// panels of 128; a panel holds its K blocks of 16 elements one after another,
+// each block as 128 rows x 32 bytes (the two 8-element halves of the block,
+// swapped for rows with ((i >> 2) ^ (i >> 3)) & 1 set).  A contraction stage
+// (one K block of one panel) is then a contiguous 4 KB run that the
+// contraction kernel copies linearly into LDS, where the swap spreads the
+// 32x32 MFMA fragment reads of 16 consecutive rows over all LDS banks; and
+// the whole K range of a panel is one contiguous 64 KB run, so the K blocks
+// of a tile never alias to the same L2 sets.
+__host__ __device__ constexpr int row_swizzle(int64_t i) { return (int)(((i >> 2) ^ (i >> 3)) & 1); }
+__host__ __device__ constexpr int64_t blocked_index(int64_t i, int64_t k, int64_t kp) {
+    return (((i >> 7) * (kp >> 4) + (k >> 4)) * 128 + (i & 127)) * 16 +
+           ((((k >> 3) & 1) ^ row_swizzle(i)) << 3) + (k & 7);
 }
 __host__ __device__ constexpr int elem_bytes(int prec) {
     return prec == P_F64 ? 8 : prec == P_F32 ? 4 : prec == P_FP8 ? 1 : 2;
@@ -22,7 +44,7 @@ __host__ __device__ constexpr int planes(int prec) { return prec == P_SPLIT ? 2 
 constexpr int kTransformK = 16;   // inner-dimension granularity of the transform GEMM
 constexpr int kTransformTile = 64;
 constexpr int kNPad = 128;        // spectral points are padded to this multiple
-constexpr int kCenterCols = 64;   // columns per workgroup of the centring kernel
+constexpr int kCenterCols = 32;   // columns per workgroup of the centring kernel
 
 // Transform table of one perturbation length: rows [0, kp) are the operand
 // transform T1, rows [kp, 2kp) the asynchronous operand transform T2, rows up
@@ -74,6 +96,8 @@ struct CorrJob {
     int32_t layout;     // Layout
     int32_t out_f64;
     int32_t group;      // column tiles per L2 group
+    int32_t scaled;     // operands carry per-band power-of-two scales
+    int32_t pad0;
     int64_t ntiles;
     double c;           // FP64 normalization of the contraction
 };

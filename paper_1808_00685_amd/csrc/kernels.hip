@@ -151,8 +151,37 @@ __device__ inline double jqrow(const TwiddleView& tw, int64_t r, int64_t l) {
     return (r & 1) ? M_SQRT2 * tw.s[idx] : M_SQRT2 * tw.c[idx];
 }
 
-__device__ inline double table_entry(const TableJob& T, const TwiddleView& tw, int64_t r,
-                                     int64_t j) {
+// sum_{l != j} Q[k][l] / (pi (j - l)) with h[d + m] = 1/(pi d) from LDS and
+// the twiddle index p*l mod m advanced incrementally.
+__device__ inline double qn_entry(const TwiddleView& tw, const double* h, int64_t k, int64_t j) {
+    const int64_t m = tw.m;
+    if (k == 0) {
+        double s = 0.0;
+        for (int64_t l = 0; l < m; ++l)
+            if (l != j) s += h[j - l + m];
+        return s;
+    }
+    if ((m & 1) == 0 && k == m - 1) {
+        double s = 0.0;
+        for (int64_t l = 0; l < m; ++l)
+            if (l != j) s += ((l & 1) ? -1.0 : 1.0) * h[j - l + m];
+        return s;
+    }
+    const int64_t p = (k + 1) >> 1;
+    const double* t = (k & 1) ? tw.c : tw.s;
+    const double sg = (k & 1) ? M_SQRT2 : -M_SQRT2;
+    double s = 0.0;
+    int64_t idx = 0;
+    for (int64_t l = 0; l < m; ++l) {
+        if (l != j) s += t[idx] * h[j - l + m];
+        idx += p;
+        if (idx >= m) idx -= m;
+    }
+    return sg * s;
+}
+
+__device__ inline double table_entry(const TableJob& T, const TwiddleView& tw, const double* h,
+                                     int64_t r, int64_t j) {
     const int64_t m = T.m;
     if (j >= m) return 0.0;
     if (r < T.kp) {
@@ -164,12 +193,9 @@ __device__ inline double table_entry(const TableJob& T, const TwiddleView& tw, i
     if (T.basis == B_FOURIER) {
         if (T.hilbert == H_CIRCULAR) return jqrow(tw, k, j);
         // (Q N)[k][j] = sum_{l != j} Q[k][l] / (pi (j - l))
-        double s = 0.0;
-        for (int64_t l = 0; l < m; ++l)
-            if (l != j) s += qrow(tw, k, l) / (M_PI * (double)(j - l));
-        return s;
+        return qn_entry(tw, h, k, j);
     }
-    if (T.hilbert == H_NODA) return k == j ? 0.0 : 1.0 / (M_PI * (double)(j - k));
+    if (T.hilbert == H_NODA) return k == j ? 0.0 : h[j - k + m];
     // circular kernel in the time basis: (1/m) sum_r Q[r][k] (J Q)[r][j]
     double s = 0.0;
     for (int64_t q = 0; q < m; ++q) s += qrow(tw, q, k) * jqrow(tw, q, j);
@@ -182,6 +208,7 @@ template <class Src>
 __global__ __launch_bounds__(256) void tables_kernel(Src src) {
     __shared__ double tc[kMaxTwiddle];
     __shared__ double ts[kMaxTwiddle];
+    __shared__ double hh[2 * kMaxTwiddle];   // hh[d + m] = 1/(pi d), d != 0
     int lb;
     const TableJob T = src.get(blockIdx.x, lb);
     if (blockIdx.x == 0 && threadIdx.x == 0 && src.counter) *src.counter = 0;
@@ -191,13 +218,15 @@ __global__ __launch_bounds__(256) void tables_kernel(Src src) {
         tc[i] = cv;
         ts[i] = sv;
     }
+    for (int64_t d = (int64_t)threadIdx.x - T.m; d < T.m; d += blockDim.x)
+        hh[d + T.m] = d == 0 ? 0.0 : 1.0 / (M_PI * (double)d);
     __syncthreads();
     const TwiddleView tw{tc, ts, T.m};
     const int64_t e = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)T.rows_pad * T.kt;
     if (e >= total) return;
     const int64_t r = e / T.kt, j = e % T.kt;
-    const double v = table_entry(T, tw, r, j);
+    const double v = table_entry(T, tw, hh, r, j);
     if (T.f64) ((double*)T.table)[e] = v;
     else ((float*)T.table)[e] = (float)v;
 }
@@ -220,34 +249,48 @@ __device__ inline float pow2_scale(double qhalf, double bound) {
     return ldexpf(1.0f, e);
 }
 
+// Workgroup: 32 spectral points x 8 row groups.  Pass 1 sums each column
+// (FP64), pass 2 re-reads, subtracts the mean (FP64) and writes the centred
+// column transposed (its m values contiguous) through an LDS tile.
 template <class Src>
 __global__ __launch_bounds__(256) void center_kernel(Src src) {
-    __shared__ double red[4][kCenterCols];
-    __shared__ double tile[kCenterCols][kCenterCols + 1];
+    constexpr int CW = kCenterCols, G = 256 / kCenterCols;
+    __shared__ double red[G][CW];
+    __shared__ double tile[CW][64 + 1];
     int lb;
     const PrepJob J = src.get(blockIdx.x, lb);
-    const int tid = threadIdx.x, c = tid & 63, g = tid >> 6;
-    const int64_t col = (int64_t)lb * kCenterCols + c;
+    const int tid = threadIdx.x, c = tid % CW, g = tid / CW;
+    const int64_t col = (int64_t)lb * CW + c;
     const bool valid = col < J.n;
 
     double mean = 0.0;
     if (J.ref) {
         mean = valid ? J.ref[col] : 0.0;
     } else {
-        double s = 0.0;
-        if (valid)
-            for (int64_t j = g; j < J.m; j += 4) s += load_in(J, j, col);
-        red[g][c] = s;
+        double s0 = 0.0, s1 = 0.0;
+        if (valid) {
+            int64_t j = g;
+            for (; j + G < J.m; j += 2 * G) {
+                s0 += load_in(J, j, col);
+                s1 += load_in(J, j + G, col);
+            }
+            if (j < J.m) s0 += load_in(J, j, col);
+        }
+        red[g][c] = s0 + s1;
         __syncthreads();
-        mean = ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) / (double)J.m;
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) t += red[q][c];
+        mean = t / (double)J.m;
         __syncthreads();
     }
 
     double nrm = 0.0;
-    const int cc = tid >> 2, qq = tid & 3;
-    const int64_t ocol = (int64_t)lb * kCenterCols + cc;
+    const int cc = tid / G, part = tid % G;        // writer: column cc, 8 values
+    const int64_t ocol = (int64_t)lb * CW + cc;
     for (int j0 = 0; j0 < J.kt; j0 += 64) {
-        for (int jj = g; jj < 64; jj += 4) {
+#pragma unroll
+        for (int jj = g; jj < 64; jj += G) {
             const int64_t j = j0 + jj;
             double v = 0.0;
             if (valid && j < J.m) v = load_in(J, j, col) - mean;
@@ -255,23 +298,19 @@ __global__ __launch_bounds__(256) void center_kernel(Src src) {
             tile[c][jj] = v;
         }
         __syncthreads();
-        const int jb = j0 + qq * 16;
+        const int jb = j0 + part * 8;
         if (jb < J.kt) {
             if (J.t_f64) {
                 double* dst = (double*)J.yt + ocol * J.kt + jb;
 #pragma unroll
-                for (int e = 0; e < 16; e += 2) {
-                    double2 v2 = make_double2(tile[cc][qq * 16 + e], tile[cc][qq * 16 + e + 1]);
-                    *(double2*)(dst + e) = v2;
-                }
+                for (int e = 0; e < 8; e += 2)
+                    *(double2*)(dst + e) = make_double2(tile[cc][part * 8 + e], tile[cc][part * 8 + e + 1]);
             } else {
                 float* dst = (float*)J.yt + ocol * J.kt + jb;
 #pragma unroll
-                for (int e = 0; e < 16; e += 4) {
-                    float4 v4 = make_float4((float)tile[cc][qq * 16 + e], (float)tile[cc][qq * 16 + e + 1],
-                                            (float)tile[cc][qq * 16 + e + 2], (float)tile[cc][qq * 16 + e + 3]);
-                    *(float4*)(dst + e) = v4;
-                }
+                for (int e = 0; e < 8; e += 4)
+                    *(float4*)(dst + e) = make_float4((float)tile[cc][part * 8 + e], (float)tile[cc][part * 8 + e + 1],
+                                                      (float)tile[cc][part * 8 + e + 2], (float)tile[cc][part * 8 + e + 3]);
             }
         }
         __syncthreads();
@@ -279,7 +318,9 @@ __global__ __launch_bounds__(256) void center_kernel(Src src) {
     red[g][c] = nrm;
     __syncthreads();
     if (g == 0) {
-        const double tot = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+        double tot = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) tot += red[q][c];
         const double r = sqrt(tot);
         float sa = 1.0f, sb = 1.0f;
         if (J.scale) {
@@ -399,7 +440,8 @@ __global__ __launch_bounds__(256) void transform_kernel(Src src) {
                 for (int q = 0; q < 4; ++q) {
                     const int64_t i = i0 + a * 16 + kg * 4 + q;
                     const float s = isB ? J.sB[i] : J.sA[i];
-                    store_operand<P>(J, isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, i * J.kp + k,
+                    const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
+                    store_operand<P>(J, isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx,
                                      acc[a][b][q] * s);
                 }
             }
@@ -454,14 +496,34 @@ __device__ inline void store_val(void* base, int64_t idx, double v, int f64) {
 __device__ inline int64_t packed_index(int64_t i, int64_t j, int64_t n) {
     return i * n - (i * (i - 1)) / 2 + (j - i);
 }
+// Start of packed row i minus i, so that element (i, j) is at base + j.
+__device__ inline int64_t packed_row_base(int64_t i, int64_t n) {
+    return i * n - (i * (i - 1)) / 2 - i;
+}
 
-// Epilogue for one element: FP64 normalization, zero asynchronous diagonal,
-// exact mirror (FULL) or packed (UPPER) stores for homocorrelation.
-__device__ inline void emit(const CorrJob& C, int64_t i, int64_t j, double vphi, double vpsi) {
+// 1/s for a power-of-two scale s, exactly.
+__device__ inline double inv_pow2(float s) { return ldexp(1.0, -ilogbf(s)); }
+
+// FP64 factors of the epilogue: Phi(i,j) = acc * c / (sL_i sRA_j),
+// Psi(i,j) = acc * c / (sL_i sRB_j).  Scales are powers of two, so the
+// factors are exact and applying them adds no rounding.
+__device__ inline void col_factors(const CorrJob& C, int64_t j, double& fa, double& fb) {
+    if (!C.scaled) {
+        fa = fb = C.c;
+        return;
+    }
+    fa = C.c * inv_pow2(C.sRA[j]);
+    fb = C.c * inv_pow2(C.sRB[j]);
+}
+__device__ inline double row_factor(const CorrJob& C, int64_t i) {
+    return C.scaled ? inv_pow2(C.sL[i]) : 1.0;
+}
+
+// Epilogue for one element with every check: bounds, zero asynchronous
+// diagonal, exact mirror (FULL) or packed (UPPER) stores for homocorrelation.
+// vphi, vpsi are already normalized.
+__device__ inline void emit(const CorrJob& C, int64_t i, int64_t j, double phi, double psi) {
     if (i >= C.n1 || j >= C.n2) return;
-    const double f = C.c / ((double)C.sL[i]);
-    const double phi = vphi * f / (double)C.sRA[j];
-    double psi = vpsi * f / (double)C.sRB[j];
     if (!C.homo) {
         store_val(C.phi, i * C.ld_out + j, phi, C.out_f64);
         store_val(C.psi, i * C.ld_out + j, psi, C.out_f64);
@@ -539,16 +601,318 @@ __device__ inline void corr_tile(const CorrJob& C, int I, int J) {
     }
 
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+    for (int b = 0; b < FN; ++b) {
+        const int64_t j = j0 + b * 16 + row16;
+        double fa, fb;
+        col_factors(C, j, fa, fb);
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t j = j0 + b * 16 + row16;
+        for (int a = 0; a < FM; ++a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t i = i0 + a * 16 + (P == P_F64 ? kg + 4 * q : kg * 4 + q);
-                emit(C, i, j, (double)ap[a][b][q], (double)aq[a][b][q]);
+                const double rf = row_factor(C, i);
+                emit(C, i, j, (double)ap[a][b][q] * fa * rf, (double)aq[a][b][q] * fb * rf);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged contraction for the 16-bit formats (split BF16, BF16, FP16).
+//
+// Workgroup: 4 waves (2 x 2), output tile 128 x 128 of Phi and of Psi; each
+// wave owns 64 x 64 of both (2 x 2 blocks of v_mfma_f32_32x32x16).  The
+// contraction runs over K blocks of 16.  Each block's operand rows (left A
+// rows of tile I, right A and B rows of tile J, hi and lo planes for the
+// split form) are 4 KB runs of the K-blocked layout, copied straight into
+// LDS with global_load_lds_dwordx4 (no register staging) through a 3-stage
+// ring: the copies of blocks kb+1 and kb+2 are in flight while block kb
+// feeds the MFMAs.  Each wave waits only for its own copies of block kb
+// (vmcnt) and a bare s_barrier publishes them; a full __syncthreads would
+// also drain the prefetches.
+// ---------------------------------------------------------------------------
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+#define AS_GLOBAL(p) ((const __attribute__((address_space(1))) void*)(p))
+#define AS_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+template <int P> struct Wide;
+template <> struct Wide<P_SPLIT> { using T = bf8; };
+template <> struct Wide<P_BF16> { using T = bf8; };
+template <> struct Wide<P_F16> { using T = h8; };
+
+template <int P>
+__device__ inline void mma32(f16v& acc, const typename Wide<P>::T& a, const typename Wide<P>::T& b) {
+    if constexpr (P == P_F16) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+    else acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+}
+
+constexpr int kStages = 3;
+template <int P> constexpr int stage_bytes() { return 3 * planes(P) * 4096; }
+constexpr int kOutPitch = 132;   // floats per row of the LDS output tile (128 + 4)
+// LDS of a contraction workgroup: the operand ring, reused by the output tile
+template <int P> constexpr int corr2_lds_bytes() {
+    return kStages * stage_bytes<P>() > 128 * kOutPitch * 4 ? kStages * stage_bytes<P>()
+                                                              : 128 * kOutPitch * 4;
+}
+
+template <int N>
+__device__ inline void wait_vmcnt() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ inline void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+// Barrier after this wave's own LDS writes (ds_write is asynchronous): wait
+// for them (lgkmcnt), but not for outstanding global stores (vmcnt).
+__device__ inline void lds_write_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Epilogue of one 128 x 128 output tile of Phi (psi = false) or Psi.
+// The waves normalize their accumulators in FP64 (x c / (sL_i sR_j)), round
+// once to the output type and write them into an LDS tile (the operand ring
+// is free by then); all 256 threads then store rows of the tile as
+// contiguous runs: 16-byte stores where the destination allows, the mirror
+// of a FULL homocorrelation read transposed from the same tile.  Accumulator
+// register r of lane l holds row 8(r/4) + 4(l/32) + r%4 and column l%32 of
+// its 32 x 32 block.
+
+__device__ inline void put4(void* base, int64_t idx, float4 v, bool f64, bool aligned) {
+    if (f64) {
+        double* d = (double*)base + idx;
+        if (aligned) {
+            *(double2*)d = make_double2(v.x, v.y);
+            *(double2*)(d + 2) = make_double2(v.z, v.w);
+        } else {
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+    } else {
+        float* f = (float*)base + idx;
+        if (aligned) *(float4*)f = v;
+        else { f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w; }
+    }
+}
+__device__ inline void put1(void* base, int64_t idx, float v, bool f64) {
+    if (f64) ((double*)base)[idx] = v;
+    else ((float*)base)[idx] = v;
+}
+
+__device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][2], char* lds, bool psi) {
+    float* T = (float*)lds;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wi = w >> 1, wj = w & 1, g = lane >> 5;
+    const bool homo = C.homo;
+    const bool diag = homo && I == J;
+    lds_barrier();   // previous readers of the LDS are done
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int jl = wj * 64 + b * 32 + (lane & 31);
+        double fc = C.c;
+        if (C.scaled) fc *= inv_pow2(psi ? C.sRB[(int64_t)J * 128 + jl] : C.sRA[(int64_t)J * 128 + jl]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int il = wi * 64 + a * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+                double f = fc;
+                if (C.scaled) f *= inv_pow2(C.sL[(int64_t)I * 128 + il]);
+                float v = (float)((double)acc[a][b][r] * f);
+                if (psi && diag && il == jl) v = 0.0f;
+                T[il * kOutPitch + jl] = v;
+            }
+    }
+    lds_write_barrier();
+    void* out = psi ? C.psi : C.phi;
+    const bool f64 = C.out_f64;
+    const int cl = (threadIdx.x & 31) * 4;   // 4 consecutive columns per thread
+    const int rsub = threadIdx.x >> 5;        // 8 rows per pass
+    const int64_t i0 = (int64_t)I * 128, j0 = (int64_t)J * 128;
+    const bool inside = i0 + 128 <= C.n1 && j0 + 128 <= C.n2;
+    for (int pass = 0; pass < 16; ++pass) {
+        const int rl = pass * 8 + rsub;
+        const int64_t i = i0 + rl, j = j0 + cl;
+        const float4 v = *(const float4*)(T + rl * kOutPitch + cl);
+        if (!homo || C.layout == L_FULL) {
+            // direct rows (homo: the upper part; diagonal tiles mask i > j)
+            const int64_t idx = i * C.ld_out + j;
+            if (inside && !diag) {
+                put4(out, idx, v, f64, ((idx & 3) == 0) && ((C.ld_out & 3) == 0));
+            } else if (i < C.n1) {
+                const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t jj = j + q;
+                    if (jj >= C.n2) break;
+                    if (diag && jj < i) continue;
+                    put1(out, idx + q, e[q], f64);
+                }
+            }
+            if (homo) {
+                // mirror tile (J, I): row jm = j0 + rl, columns i0 + cl..+3,
+                // value -(+)T[c][rl] for Psi (Phi); diagonal tiles fill i > j
+                const int64_t jm = j0 + rl, im = i0 + cl;
+                const float sg = psi ? -1.0f : 1.0f;
+                const float4 t = make_float4(sg * T[(cl + 0) * kOutPitch + rl], sg * T[(cl + 1) * kOutPitch + rl],
+                                             sg * T[(cl + 2) * kOutPitch + rl], sg * T[(cl + 3) * kOutPitch + rl]);
+                const int64_t midx = jm * C.ld_out + im;
+                if (inside && !diag) {
+                    put4(out, midx, t, f64, ((midx & 3) == 0) && ((C.ld_out & 3) == 0));
+                } else if (jm < C.n1) {
+                    const float e[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t ii = im + q;
+                        if (ii >= C.n1) break;
+                        if (diag && ii >= jm) continue;   // strictly lower part (row jm > col ii)
+                        put1(out, midx + q, e[q], f64);
+                    }
+                }
+            }
+        } else {
+            // UPPER_PACKED: element (i, j) at rowbase(i) + j, j >= i
+            if (i < C.n1) {
+                const int64_t idx = packed_row_base(i, C.n1) + j;
+                if (inside && !diag) {
+                    put4(out, idx, v, f64, (idx & 3) == 0);
+                } else {
+                    const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t jj = j + q;
+                        if (jj >= C.n2) break;
+                        if (jj < i) continue;
+                        put1(out, idx + q, e[q], f64);
+                    }
+                }
             }
         }
+    }
+}
+
+template <int P>
+__device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
+    using FT = typename Wide<P>::T;
+    constexpr int PL = planes(P);
+    constexpr int OPS = 3 * PL;          // operand planes per stage: (L, RA, RB) x planes
+    constexpr int SB = stage_bytes<P>();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wi = w >> 1, wj = w & 1;
+    const int nkb = C.kp >> 4;
+
+    // global source of this wave's 1 KB part (rows w*32..w*32+31) of each
+    // plane's stage; stage kb of a panel is 4 KB after stage kb-1
+    const char* src[OPS];
+#pragma unroll
+    for (int t = 0; t < OPS; ++t) {
+        const int which = t % 3, plane = t / 3;
+        const void* b = which == 0 ? (plane ? C.L1 : C.L0)
+                                   : which == 1 ? (plane ? C.RA1 : C.RA0) : (plane ? C.RB1 : C.RB0);
+        const int64_t panel = which == 0 ? (int64_t)I : (int64_t)J;
+        src[t] = (const char*)b + panel * nkb * 4096 + w * 1024 + lane * 16;
+    }
+    auto issue = [&](int kb) {
+        char* dst = lds + (kb % kStages) * SB + w * 1024;
+#pragma unroll
+        for (int t = 0; t < OPS; ++t)
+            __builtin_amdgcn_global_load_lds(AS_GLOBAL(src[t] + kb * 4096), AS_LDS(dst + t * 4096), 16, 0, 0);
+    };
+
+    // LDS byte offsets of this lane's fragment rows (K-block half g = lane/32)
+    const int g = lane >> 5;
+    int offA[2], offB[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int ra = wi * 64 + a * 32 + (lane & 31);
+        const int rb = wj * 64 + a * 32 + (lane & 31);
+        offA[a] = ra * 32 + ((g ^ row_swizzle(ra)) << 4);
+        offB[a] = rb * 32 + ((g ^ row_swizzle(rb)) << 4);
+    }
+
+    f16v ap[2][2], aq[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            ap[a][b] = f16v{};
+            aq[a][b] = f16v{};
+        }
+
+    lds_barrier();   // the ring is free (previous tile of a persistent loop)
+    issue(0);
+    if (nkb > 1) issue(1);
+    for (int kb = 0; kb < nkb; ++kb) {
+        if (kb + 1 < nkb) wait_vmcnt<OPS>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        if (kb + 2 < nkb) issue(kb + 2);
+        const char* st = lds + (kb % kStages) * SB;
+        FT la[PL][2], ra[PL][2], rb[PL][2];
+#pragma unroll
+        for (int p = 0; p < PL; ++p)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                la[p][a] = *(const FT*)(st + (3 * p + 0) * 4096 + offA[a]);
+                ra[p][a] = *(const FT*)(st + (3 * p + 1) * 4096 + offB[a]);
+                rb[p][a] = *(const FT*)(st + (3 * p + 2) * 4096 + offB[a]);
+            }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                mma32<P>(ap[a][b], la[0][a], ra[0][b]);
+                mma32<P>(aq[a][b], la[0][a], rb[0][b]);
+                if constexpr (PL == 2) {
+                    mma32<P>(ap[a][b], la[0][a], ra[1][b]);
+                    mma32<P>(aq[a][b], la[0][a], rb[1][b]);
+                    mma32<P>(ap[a][b], la[1][a], ra[0][b]);
+                    mma32<P>(aq[a][b], la[1][a], rb[0][b]);
+                }
+            }
+    }
+
+    // epilogue through LDS, one output at a time
+    stage_out(C, I, J, ap, lds, false);
+    stage_out(C, I, J, aq, lds, true);
+}
+
+template <int P>
+__global__ __launch_bounds__(256, 2) void corr2_kernel(CorrJob C) {
+    __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P>()];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int I, J;
+    if (C.homo) decode_upper(t, C.tiles_i, C.group, I, J);
+    else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
+    corr2_tile<P>(C, I, J, lds);
+}
+
+template <int P>
+__global__ __launch_bounds__(256, 2) void corr2_persistent_kernel(const CorrJob* jobs,
+                                                                   const int64_t* tile_start,
+                                                                   int count, int64_t total,
+                                                                   int* counter) {
+    __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P>()];
+    __shared__ int64_t s_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+        __syncthreads();
+        const int64_t t = s_t;
+        __syncthreads();
+        if (t >= total) break;
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const CorrJob C = jobs[lo];
+        int I, J;
+        decode_upper(t - tile_start[lo], C.tiles_i, C.group, I, J);
+        corr2_tile<P>(C, I, J, lds);
+    }
 }
 
 template <int P, int FM, int FN>
@@ -627,11 +991,17 @@ hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipSt
     return launch_transform_t(prec, src, blocks, s);
 }
 
-#define CORR_CASES(X)                                                          \
-    X(P_F64, 2, 2) X(P_F32, 4, 4) X(P_SPLIT, 4, 4) X(P_BF16, 4, 4) X(P_F16, 4, 4) \
-    X(P_FP8, 4, 4) X(P_F32, 2, 2) X(P_SPLIT, 2, 2) X(P_BF16, 2, 2) X(P_F16, 2, 2) X(P_FP8, 2, 2)
+#define CORR_CASES(X) X(P_F64, 2, 2) X(P_F32, 4, 4) X(P_FP8, 4, 4) X(P_F32, 2, 2) X(P_FP8, 2, 2)
+#define CORR2_CASES(X) X(P_SPLIT) X(P_BF16) X(P_F16)
 
 hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s) {
+#define Y(PP)                                                                                 \
+    if (prec == PP && fm == 4 && fn == 4) {                                                   \
+        hipLaunchKernelGGL((corr2_kernel<PP>), dim3((unsigned)blocks), dim3(256), 0, s, C);   \
+        return hipGetLastError();                                                             \
+    }
+    CORR2_CASES(Y)
+#undef Y
 #define X(PP, A, B)                                                                          \
     if (prec == PP && fm == A && fn == B) {                                                  \
         hipLaunchKernelGGL((corr_kernel<PP, A, B>), dim3((unsigned)blocks), dim3(256), 0, s, C); \
@@ -645,6 +1015,14 @@ hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t block
 hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
                                   const int64_t* tile_start, int count, int64_t total,
                                   int* counter, int blocks, hipStream_t s) {
+#define Y(PP)                                                                                 \
+    if (prec == PP && fm == 4 && fn == 4) {                                                   \
+        hipLaunchKernelGGL((corr2_persistent_kernel<PP>), dim3(blocks), dim3(256), 0, s, jobs, \
+                           tile_start, count, total, counter);                                \
+        return hipGetLastError();                                                             \
+    }
+    CORR2_CASES(Y)
+#undef Y
 #define X(PP, A, B)                                                                         \
     if (prec == PP && fm == A && fn == B) {                                                 \
         hipLaunchKernelGGL((corr_persistent_kernel<PP, A, B>), dim3(blocks), dim3(256), 0, s, jobs, \
@@ -657,6 +1035,9 @@ hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
 }
 
 int corr_variant_supported(int prec, int fm, int fn) {
+#define Y(PP) if (prec == PP && fm == 4 && fn == 4) return 1;
+    CORR2_CASES(Y)
+#undef Y
 #define X(PP, A, B) if (prec == PP && fm == A && fn == B) return 1;
     CORR_CASES(X)
 #undef X
@@ -665,6 +1046,14 @@ int corr_variant_supported(int prec, int fm, int fn) {
 
 int persistent_blocks_per_cu(int prec, int fm, int fn) {
     int n = 0;
+#define Y(PP)                                                                             \
+    if (prec == PP && fm == 4 && fn == 4) {                                               \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr2_persistent_kernel<PP>, 256, 0) \
+            != hipSuccess) n = 1;                                                         \
+        return n > 0 ? n : 1;                                                             \
+    }
+    CORR2_CASES(Y)
+#undef Y
 #define X(PP, A, B)                                                                      \
     if (prec == PP && fm == A && fn == B) {                                              \
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr_persistent_kernel<PP, A, B>, 256, 0) \

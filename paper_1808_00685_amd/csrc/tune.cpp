@@ -64,9 +64,11 @@ int tune_lookup(int prec, int64_t m, int64_t n) {
     for (const Rule& r : g_rules)
         if (r.prec == prec && m <= r.m_max && n <= r.n_max) {
             if (prec == P_F64 && r.tile != 1) continue;
+            if (blocked_layout(prec) && r.tile != 2) continue;
             return r.tile;
         }
     if (prec == P_F64) return 1;
+    if (blocked_layout(prec)) return 2;
     return n <= 1024 ? 1 : 2;
 }
 
