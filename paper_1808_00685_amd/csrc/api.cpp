@@ -272,8 +272,11 @@ PrepJob make_prep_job(const corr2d_plan_s* p, const Geo& g, const SetLayout& s, 
 }
 
 int center_blocks(const Geo& g) { return (int)(g.n_pad / kCenterCols); }
-int transform_blocks(const Geo& g) {
-    return (int)((g.n_pad / kTransformTile) * (g.rows_pad / kTransformTile));
+// Workgroups of the transform GEMM: FP64 uses 64 x 64 tiles, the FP32
+// kernel 64 x 256 (spectral points x transform rows).
+int transform_blocks(const Geo& g, int prec) {
+    if (prec == CORR2D_PREC_F64) return (int)((g.n_pad / kTransformTile) * (g.rows_pad / kTransformTile));
+    return (int)((g.n_pad / 64) * ((g.rows_pad + 255) / 256));
 }
 
 int64_t triangle_tiles(int64_t T) { return T * (T + 1) / 2; }
@@ -563,7 +566,7 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
-    hipError_t e = launch_tables(ts, ts.blocks0, s);
+    hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     PrepSrcInline ps{};
@@ -572,7 +575,7 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     ps.blocks0 = center_blocks(p->g1);
     e = launch_center(ps, ps.blocks0, s);
     if (e != hipSuccess) return device_fail(e, "center launch");
-    ps.blocks0 = transform_blocks(p->g1);
+    ps.blocks0 = transform_blocks(p->g1, p->d.prec);
     e = launch_transform(p->d.prec, ps, ps.blocks0, s);
     if (e != hipSuccess) return device_fail(e, "transform launch");
 
@@ -604,7 +607,7 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
-    hipError_t e = launch_tables(ts, ts.blocks0, s);
+    hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     PrepSrcInline ps{};
@@ -614,8 +617,8 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     ps.blocks0 = center_blocks(p->g1);
     e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
     if (e != hipSuccess) return device_fail(e, "center launch");
-    ps.blocks0 = transform_blocks(p->g1);
-    e = launch_transform(p->d.prec, ps, ps.blocks0 + transform_blocks(p->g2), s);
+    ps.blocks0 = transform_blocks(p->g1, p->d.prec);
+    e = launch_transform(p->d.prec, ps, ps.blocks0 + transform_blocks(p->g2, p->d.prec), s);
     if (e != hipSuccess) return device_fail(e, "transform launch");
 
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g2, p->s2, ws, phi, psi, false, p->c, p->tile,
@@ -684,7 +687,7 @@ void fill_blob(corr2d_plan_s* p, const void* y_base, void* phi_base, void* psi_b
         cs[r] = cb;
         cb += center_blocks(I.g);
         xs[r] = xb;
-        xb += transform_blocks(I.g);
+        xb += transform_blocks(I.g, p->d.prec);
         void* ph = (char*)phi_base + I.it.out_offset * osz;
         void* ps = (char*)psi_base + I.it.out_offset * osz;
         cj[r] = make_corr_job(p, I.g, I.s, I.g, I.s, ws, ph, ps, true, I.c, I.tile, I.it.n,
@@ -711,7 +714,7 @@ corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
     ta.start = (const int32_t*)(dev + L.tstart);
     ta.count = (int32_t)nd;
     ta.counter = counter;
-    e = launch_tables(ta, ((const int32_t*)(h + L.tstart))[nd], s);
+    e = launch_tables(ta, ((const int32_t*)(h + L.tstart))[nd], *std::max_element(p->distinct_m.begin(), p->distinct_m.end()), s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     PrepSrcArray pa{};
@@ -748,7 +751,7 @@ corr2d_status enqueue_sequential(corr2d_plan_s* p, const void* y_base, void* phi
         ts.j[0] = make_table_job(p, I.g, ws, I.table_off);
         ts.count = 1;
         ts.blocks0 = table_blocks(I.g);
-        hipError_t e = launch_tables(ts, ts.blocks0, s);
+        hipError_t e = launch_tables(ts, ts.blocks0, I.g.m, s);
         if (e != hipSuccess) return device_fail(e, "tables launch");
         PrepSrcInline ps{};
         ps.j[0] = make_prep_job(p, I.g, I.s, (const char*)y_base + I.it.in_offset * isz, I.it.ld_in,
@@ -757,7 +760,7 @@ corr2d_status enqueue_sequential(corr2d_plan_s* p, const void* y_base, void* phi
         ps.blocks0 = center_blocks(I.g);
         e = launch_center(ps, ps.blocks0, s);
         if (e != hipSuccess) return device_fail(e, "center launch");
-        ps.blocks0 = transform_blocks(I.g);
+        ps.blocks0 = transform_blocks(I.g, p->d.prec);
         e = launch_transform(p->d.prec, ps, ps.blocks0, s);
         if (e != hipSuccess) return device_fail(e, "transform launch");
         CorrJob C = make_corr_job(p, I.g, I.s, I.g, I.s, ws, (char*)phi_base + I.it.out_offset * osz,

@@ -130,7 +130,7 @@ struct TwiddleView {
 // 0 < p < m/2, and row m-1 of an even m is the Nyquist bin.  With this
 // packing the weighted half-spectrum sum of Eq. (symmeFT) is a plain dot
 // product of rows, and Q^T Q = m I.
-__device__ inline double qrow(const TwiddleView& tw, int64_t r, int64_t l) {
+__device__ inline double qrow(const TwiddleView tw, int64_t r, int64_t l) {
     const int64_t m = tw.m;
     if (r == 0) return 1.0;
     if ((m & 1) == 0 && r == m - 1) return (l & 1) ? -1.0 : 1.0;
@@ -142,7 +142,7 @@ __device__ inline double qrow(const TwiddleView& tw, int64_t r, int64_t l) {
 // Row r of J Q: each (Re, Im) pair becomes (-Im, Re); DC and Nyquist vanish.
 // A1^T (J A2) is then the imaginary part of the weighted sum of
 // F1 conj(F2) -- the circular asynchronous kernel of the m-point route.
-__device__ inline double jqrow(const TwiddleView& tw, int64_t r, int64_t l) {
+__device__ inline double jqrow(const TwiddleView tw, int64_t r, int64_t l) {
     const int64_t m = tw.m;
     if (r == 0) return 0.0;
     if ((m & 1) == 0 && r == m - 1) return 0.0;
@@ -153,7 +153,7 @@ __device__ inline double jqrow(const TwiddleView& tw, int64_t r, int64_t l) {
 
 // sum_{l != j} Q[k][l] / (pi (j - l)) with h[d + m] = 1/(pi d) from LDS and
 // the twiddle index p*l mod m advanced incrementally.
-__device__ inline double qn_entry(const TwiddleView& tw, const double* h, int64_t k, int64_t j) {
+__device__ inline double qn_entry(const TwiddleView tw, const double* h, int64_t k, int64_t j) {
     const int64_t m = tw.m;
     if (k == 0) {
         double s = 0.0;
@@ -180,7 +180,7 @@ __device__ inline double qn_entry(const TwiddleView& tw, const double* h, int64_
     return sg * s;
 }
 
-__device__ inline double table_entry(const TableJob& T, const TwiddleView& tw, const double* h,
+__device__ inline double table_entry(const TableJob& T, const TwiddleView tw, const double* h,
                                      int64_t r, int64_t j) {
     const int64_t m = T.m;
     if (j >= m) return 0.0;
@@ -204,13 +204,16 @@ __device__ inline double table_entry(const TableJob& T, const TwiddleView& tw, c
 
 constexpr int kMaxTwiddle = 4096;
 
+// Dynamic LDS: cos and sin of 2 pi i / m (m entries each), then
+// hh[d + m] = 1/(pi d) for -m < d < m (2m entries); 32 m bytes in all.
 template <class Src>
 __global__ __launch_bounds__(256) void tables_kernel(Src src) {
-    __shared__ double tc[kMaxTwiddle];
-    __shared__ double ts[kMaxTwiddle];
-    __shared__ double hh[2 * kMaxTwiddle];   // hh[d + m] = 1/(pi d), d != 0
+    extern __shared__ double tw_lds[];
     int lb;
     const TableJob T = src.get(blockIdx.x, lb);
+    double* tc = tw_lds;
+    double* ts = tw_lds + T.m;
+    double* hh = tw_lds + 2 * T.m;
     if (blockIdx.x == 0 && threadIdx.x == 0 && src.counter) *src.counter = 0;
     for (int64_t i = threadIdx.x; i < T.m; i += blockDim.x) {
         double sv, cv;
@@ -250,25 +253,38 @@ __device__ inline float pow2_scale(double qhalf, double bound) {
 }
 
 // Workgroup: 32 spectral points x 8 row groups.  Pass 1 sums each column
-// (FP64), pass 2 re-reads, subtracts the mean (FP64) and writes the centred
-// column transposed (its m values contiguous) through an LDS tile.
-template <class Src>
-__global__ __launch_bounds__(256) void center_kernel(Src src) {
-    constexpr int CW = kCenterCols, G = 256 / kCenterCols;
+// (FP64); pass 2 subtracts the mean (FP64) and writes the centred column
+// transposed (its m values contiguous) through an LDS tile.  For m <= 256
+// (CACHE) the values read in pass 1 stay in registers for pass 2.
+template <class Src, bool CACHE>
+__device__ inline void center_body(const PrepJob& J, int lb) {
+    constexpr int CW = kCenterCols, G = 256 / kCenterCols, MAXV = 32;
     __shared__ double red[G][CW];
     __shared__ double tile[CW][64 + 1];
-    int lb;
-    const PrepJob J = src.get(blockIdx.x, lb);
     const int tid = threadIdx.x, c = tid % CW, g = tid / CW;
     const int64_t col = (int64_t)lb * CW + c;
     const bool valid = col < J.n;
 
+    double vals[CACHE ? MAXV : 1];
+    if (CACHE) {
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k) {
+            const int64_t j = g + (int64_t)G * k;
+            vals[k] = (valid && j < J.m) ? load_in(J, j, col) : 0.0;
+        }
+    }
     double mean = 0.0;
     if (J.ref) {
         mean = valid ? J.ref[col] : 0.0;
     } else {
         double s0 = 0.0, s1 = 0.0;
-        if (valid) {
+        if (CACHE) {
+#pragma unroll
+            for (int k = 0; k < MAXV; k += 2) {
+                s0 += vals[k];
+                s1 += vals[k + 1];
+            }
+        } else if (valid) {
             int64_t j = g;
             for (; j + G < J.m; j += 2 * G) {
                 s0 += load_in(J, j, col);
@@ -290,10 +306,22 @@ __global__ __launch_bounds__(256) void center_kernel(Src src) {
     const int64_t ocol = (int64_t)lb * CW + cc;
     for (int j0 = 0; j0 < J.kt; j0 += 64) {
 #pragma unroll
-        for (int jj = g; jj < 64; jj += G) {
+        for (int q = 0; q < 64 / G; ++q) {
+            const int jj = g + G * q;
             const int64_t j = j0 + jj;
             double v = 0.0;
-            if (valid && j < J.m) v = load_in(J, j, col) - mean;
+            if (valid && j < J.m) {
+                if (CACHE) {
+                    // j = g + G k with k = j0/G + q; j0/G is a multiple of 8
+                    double x = 0.0;
+#pragma unroll
+                    for (int k = 0; k < MAXV; ++k)
+                        if (k == j0 / G + q) x = vals[k];
+                    v = x - mean;
+                } else {
+                    v = load_in(J, j, col) - mean;
+                }
+            }
             nrm += v * v;
             tile[c][jj] = v;
         }
@@ -330,6 +358,14 @@ __global__ __launch_bounds__(256) void center_kernel(Src src) {
         if (J.sA) J.sA[col] = sa;
         if (J.sB) J.sB[col] = sb;
     }
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void center_kernel(Src src) {
+    int lb;
+    const PrepJob J = src.get(blockIdx.x, lb);
+    if (J.m <= 256) center_body<Src, true>(J, lb);
+    else center_body<Src, false>(J, lb);
 }
 
 // =========================================================================
@@ -444,6 +480,87 @@ __global__ __launch_bounds__(256) void transform_kernel(Src src) {
                     store_operand<P>(J, isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx,
                                      acc[a][b][q] * s);
                 }
+            }
+    }
+}
+
+// FP32 transform GEMM for the reduced precisions.  Workgroup tile: 64
+// spectral points x 256 transform rows; each wave owns 64 x 64 (4 x 4 blocks
+// of v_mfma_f32_16x16x4f32) and prefetches the next K step's fragments while
+// the current step's MFMAs run.
+constexpr int kT32Cols = 256;
+
+template <int P, class Src>
+__global__ __launch_bounds__(256) void transform32_kernel(Src src) {
+    int lb;
+    const PrepJob J = src.get(blockIdx.x, lb);
+    const int rtiles = (J.rows_pad + kT32Cols - 1) / kT32Cols;
+    const int bi = lb / rtiles, br = lb % rtiles;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row16 = lane & 15, kg = lane >> 4;
+    const int64_t i0 = (int64_t)bi * 64;
+    const int64_t r0 = (int64_t)br * kT32Cols + wave * 64;
+    if (r0 >= J.rows_pad) return;
+    const float* Y = (const float*)J.yt;
+    const float* T = (const float*)J.table;
+    const float* yrow[4];
+    const float* trow[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        yrow[a] = Y + (i0 + a * 16 + row16) * J.kt + kg * 4;
+        trow[a] = T + (r0 + a * 16 + row16) * J.kt + kg * 4;
+    }
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    f4 fa[4], fb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        fa[a] = *(const f4*)(yrow[a]);
+        fb[a] = *(const f4*)(trow[a]);
+    }
+    for (int k0 = 0; k0 < J.kt; k0 += 16) {
+        f4 na[4], nb[4];
+        const bool more = k0 + 16 < J.kt;
+        if (more) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                na[a] = *(const f4*)(yrow[a] + k0 + 16);
+                nb[a] = *(const f4*)(trow[a] + k0 + 16);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][s], fb[b][s], acc[a][b], 0, 0, 0);
+        if (more) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                fa[a] = na[a];
+                fb[a] = nb[a];
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t r = r0 + b * 16 + row16;
+        if (r >= 2 * (int64_t)J.kp) continue;
+        const bool isB = r >= J.kp;
+        if (isB && !J.need_b) continue;
+        const int64_t k = isB ? r - J.kp : r;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t i = i0 + a * 16 + kg * 4 + q;
+                const float sc = isB ? J.sB[i] : J.sA[i];
+                const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
+                store_operand<P>(J, isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx, acc[a][b][q] * sc);
             }
     }
 }
@@ -954,12 +1071,12 @@ __global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* job
 // =========================================================================
 // Host launchers
 // =========================================================================
-hipError_t launch_tables(const TableSrcInline& src, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(tables_kernel<TableSrcInline>, dim3(blocks), dim3(256), 0, s, src);
+hipError_t launch_tables(const TableSrcInline& src, int blocks, int64_t max_m, hipStream_t s) {
+    hipLaunchKernelGGL(tables_kernel<TableSrcInline>, dim3(blocks), dim3(256), (size_t)(32 * max_m), s, src);
     return hipGetLastError();
 }
-hipError_t launch_tables(const TableSrcArray& src, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(tables_kernel<TableSrcArray>, dim3(blocks), dim3(256), 0, s, src);
+hipError_t launch_tables(const TableSrcArray& src, int blocks, int64_t max_m, hipStream_t s) {
+    hipLaunchKernelGGL(tables_kernel<TableSrcArray>, dim3(blocks), dim3(256), (size_t)(32 * max_m), s, src);
     return hipGetLastError();
 }
 hipError_t launch_center(const PrepSrcInline& src, int blocks, hipStream_t s) {
@@ -975,11 +1092,11 @@ template <class Src>
 static hipError_t launch_transform_t(int prec, const Src& src, int blocks, hipStream_t s) {
     switch (prec) {
     case P_F64: hipLaunchKernelGGL((transform_kernel<P_F64, Src>), dim3(blocks), dim3(256), 0, s, src); break;
-    case P_F32: hipLaunchKernelGGL((transform_kernel<P_F32, Src>), dim3(blocks), dim3(256), 0, s, src); break;
-    case P_SPLIT: hipLaunchKernelGGL((transform_kernel<P_SPLIT, Src>), dim3(blocks), dim3(256), 0, s, src); break;
-    case P_BF16: hipLaunchKernelGGL((transform_kernel<P_BF16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
-    case P_F16: hipLaunchKernelGGL((transform_kernel<P_F16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
-    case P_FP8: hipLaunchKernelGGL((transform_kernel<P_FP8, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_F32: hipLaunchKernelGGL((transform32_kernel<P_F32, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_SPLIT: hipLaunchKernelGGL((transform32_kernel<P_SPLIT, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_BF16: hipLaunchKernelGGL((transform32_kernel<P_BF16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_F16: hipLaunchKernelGGL((transform32_kernel<P_F16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_FP8: hipLaunchKernelGGL((transform32_kernel<P_FP8, Src>), dim3(blocks), dim3(256), 0, s, src); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

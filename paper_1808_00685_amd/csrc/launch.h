@@ -70,8 +70,9 @@ struct PrepSrcArray {
     }
 };
 
-hipError_t launch_tables(const TableSrcInline& src, int blocks, hipStream_t s);
-hipError_t launch_tables(const TableSrcArray& src, int blocks, hipStream_t s);
+// max_m: the largest perturbation length among the jobs (sizes the LDS)
+hipError_t launch_tables(const TableSrcInline& src, int blocks, int64_t max_m, hipStream_t s);
+hipError_t launch_tables(const TableSrcArray& src, int blocks, int64_t max_m, hipStream_t s);
 hipError_t launch_center(const PrepSrcInline& src, int blocks, hipStream_t s);
 hipError_t launch_center(const PrepSrcArray& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s);
