@@ -138,6 +138,23 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     return res
 
 
+def measured_traffic(kernel_tag="corr2_split_m256_n16384"):
+    """HBM bytes per launch of the contraction kernel from the committed PMC
+    record (FETCH_SIZE and WRITE_SIZE, each scaled by a 1 GiB copy), or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
+    src = os.path.join(ROOT, "paper_1808_00685_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(rec_path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(oracle, S, target_s):
     """The oracle's direct route on a bounded sample of output rows."""
     Y, _ = oracle.dynamic(S)
@@ -234,7 +251,8 @@ def main():
         "roofline": {
             "bound": "mfma", "kernel": "corr_kernel<split_bf16, 128x128>",
             "achieved": achieved, "peak": PEAK_TFLOPS["split_bf16"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS["split_bf16"], "traffic": None,
+            "frac": achieved / PEAK_TFLOPS["split_bf16"],
+            "traffic": measured_traffic() if (m, n) == (256, 16384) else None,
             "kernel_ms": kms,
             "algorithmic_flops_per_launch": alg,
             "executed_tflops": main_res["kernel_executed_tflops"],
