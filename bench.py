@@ -249,7 +249,7 @@ def main():
                    "m": m, "n": n, "layout": "upper_packed", "prec": "split_bf16",
                    "entries_per_step": n * (n + 1) // 2},
         "roofline": {
-            "bound": "mfma", "kernel": "corr_kernel<split_bf16, 128x128>",
+            "bound": "mfma", "kernel": f"corr2_kernel<split_bf16> ({main_res['tile']} tiles)",
             "achieved": achieved, "peak": PEAK_TFLOPS["split_bf16"], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS["split_bf16"],
             "traffic": measured_traffic() if (m, n) == (256, 16384) else None,

@@ -110,7 +110,10 @@ typedef struct corr2d_desc {
     double norm_value;  /* cF for CORR2D_NORM_CUSTOM                             */
     int32_t out_layout; /* corr2d_layout                                         */
     uint32_t flags;     /* CORR2D_FLAG_*                                         */
-    int32_t tile;       /* 0 = automatic (tuned table), else a corr2d tile id    */
+    int32_t tile;       /* 0 = automatic (tuned table); 1 = 64 x 64 output tiles
+                           (FP64, FP32, FP8); 2 = 128 x 128 (FP32, FP8) or
+                           256 x 128 (split-BF16, BF16, FP16); 3 = 128 x 128
+                           (split-BF16, BF16, FP16)                             */
     int32_t reserved;
 } corr2d_desc;
 

@@ -61,7 +61,8 @@ Geo geometry(int64_t m, int64_t n, int prec) {
     Geo g;
     g.m = m;
     g.n = n;
-    g.n_pad = round_up(n, kNPad);
+    // the 16-bit formats pair two 128-row panels in one 256-row tile
+    g.n_pad = round_up(n, blocked_layout(prec) ? 2 * kNPad : kNPad);
     g.kp = (int32_t)round_up(m, k_align(prec));
     g.kt = (int32_t)round_up(m, kTransformK);
     g.rows_pad = (int32_t)round_up(2 * (int64_t)g.kp, kTransformTile);
@@ -78,10 +79,14 @@ struct Tile {
     int id = 2, fm = 4, fn = 4;
 };
 
-Tile tile_from_id(int id) {
+// Tile id 1: 64 x 64 outputs; id 2: 128 x 128, or 256 x 128 for the 16-bit
+// formats (LDS-staged kernel, one workgroup per CU); id 3: 128 x 128 of the
+// LDS-staged kernel (two workgroups per CU).
+Tile tile_from_id(int id, int prec) {
     Tile t;
     t.id = id;
     t.fm = t.fn = (id == 1) ? 2 : 4;
+    if (id == 2 && blocked_layout(prec)) t.fm = 8;
     return t;
 }
 
@@ -158,8 +163,10 @@ corr2d_status check_common(const corr2d_desc* d) {
     if (d->flags & ~0xfu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
     if (d->prec == CORR2D_PREC_FP8_E4M3 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
         return fail(CORR2D_EUNSUPPORTED, "FP8 e4m3 requires per-band scaling (range 448)");
-    if (d->tile != 0 && d->tile != 1 && d->tile != 2)
+    if (d->tile < 0 || d->tile > 3)
         return fail(CORR2D_EINVAL, "unknown tile id %d", d->tile);
+    if (d->tile == 3 && !blocked_layout(d->prec))
+        return fail(CORR2D_EUNSUPPORTED, "tile 3 (128x128, LDS-staged) is built for the 16-bit formats only");
     if (d->tile == 2 && d->prec == CORR2D_PREC_F64)
         return fail(CORR2D_EUNSUPPORTED, "tile 2 (128x128) is not built for FP64");
     if (d->tile == 1 && blocked_layout(d->prec))
@@ -279,7 +286,9 @@ int transform_blocks(const Geo& g, int prec) {
     return (int)((g.n_pad / 64) * ((g.rows_pad + 255) / 256));
 }
 
-int64_t triangle_tiles(int64_t T) { return T * (T + 1) / 2; }
+// Tiles of the upper triangle when a row tile is R column tiles tall: row
+// tile I pairs with column tiles J >= R I of the R T column tiles.
+int64_t triangle_tiles(int64_t T, int64_t R) { return R * T * (T + 1) / 2; }
 
 CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1, const Geo& g2,
                       const SetLayout& s2, void* ws, void* phi, void* psi, bool homo, double c,
@@ -300,22 +309,22 @@ CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1
     C.n2 = g2.n;
     C.ld_out = ld_out;
     C.kp = g1.kp;
-    const int bm = 32 * tile.fm;
-    C.tiles_i = (int32_t)(g1.n_pad / bm);
-    C.tiles_j = (int32_t)(g2.n_pad / bm);
+    C.tiles_i = (int32_t)(g1.n_pad / (32 * tile.fm));
+    C.tiles_j = (int32_t)(g2.n_pad / (32 * tile.fn));
+    C.ratio = tile.fm / tile.fn;
     C.homo = homo;
     C.layout = layout;
     C.out_f64 = p->d.out_dtype == CORR2D_DTYPE_F64;
     C.group = p->group;
     C.scaled = p->scale;
-    C.ntiles = homo ? triangle_tiles(C.tiles_i) : (int64_t)C.tiles_i * C.tiles_j;
+    C.ntiles = homo ? triangle_tiles(C.tiles_i, C.ratio) : (int64_t)C.tiles_i * C.tiles_j;
     C.c = c;
     return C;
 }
 
 Tile choose_tile(const corr2d_desc* d, int64_t m, int64_t n) {
-    if (d->tile) return tile_from_id(d->tile);
-    return tile_from_id(tune_lookup(d->prec, m, n));
+    if (d->tile) return tile_from_id(d->tile, d->prec);
+    return tile_from_id(tune_lookup(d->prec, m, n), d->prec);
 }
 
 corr2d_status check_ws(const corr2d_plan_s* p, void* ws, size_t ws_bytes) {
@@ -406,13 +415,12 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     if (!hetero) {
         p->s1 = layout_set(p->g1, d->prec, t64, true, &off);
         const int64_t T = p->g1.n_pad / (32 * p->tile.fm);
-        p->ntiles = triangle_tiles(T);
+        p->ntiles = triangle_tiles(T, p->tile.fm / p->tile.fn);
     } else {
         p->g2 = geometry(d->m, d->n2, d->prec);
         p->s1 = layout_set(p->g1, d->prec, t64, false, &off);
         p->s2 = layout_set(p->g2, d->prec, t64, true, &off);
-        const int64_t bm = 32 * p->tile.fm;
-        p->ntiles = (p->g1.n_pad / bm) * (p->g2.n_pad / bm);
+        p->ntiles = (p->g1.n_pad / (32 * p->tile.fm)) * (p->g2.n_pad / (32 * p->tile.fn));
     }
     p->ws_bytes = off;
     *out = p;
@@ -474,7 +482,7 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
         I.table_off = p->table_of_m[mi];
         I.c = contraction_factor(common, I.it.m);
         I.tile = p->tile;
-        I.ntiles = triangle_tiles(I.g.n_pad / (32 * p->tile.fm));
+        I.ntiles = triangle_tiles(I.g.n_pad / (32 * p->tile.fm), p->tile.fm / p->tile.fn);
         const int64_t outn = common->out_layout == CORR2D_LAYOUT_UPPER_PACKED
                                  ? I.it.n * (I.it.n + 1) / 2 : I.it.n * I.it.n;
         p->out_elements = std::max(p->out_elements, I.it.out_offset + outn);

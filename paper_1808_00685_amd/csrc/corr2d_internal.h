@@ -17,9 +17,10 @@ __host__ __device__ constexpr bool blocked_layout(int prec) {
     return prec == P_SPLIT || prec == P_BF16 || prec == P_F16;
 }
 
-// Contraction length granularity per precision.
+// Contraction length granularity per precision (the LDS-staged kernel of
+// the 16-bit formats takes its K blocks of 16 in pairs).
 __host__ __device__ constexpr int k_align(int prec) {
-    return prec == P_FP8 ? 64 : 16;
+    return prec == P_FP8 ? 64 : blocked_layout(prec) ? 32 : 16;
 }
 
 // Panel-blocked operand layout of the 16-bit formats.  Rows are grouped in
@@ -97,7 +98,7 @@ struct CorrJob {
     int32_t out_f64;
     int32_t group;      // column tiles per L2 group
     int32_t scaled;     // operands carry per-band power-of-two scales
-    int32_t pad0;
+    int32_t ratio;      // row tile height / column tile width (homo tile order)
     int64_t ntiles;
     double c;           // FP64 normalization of the contraction
 };

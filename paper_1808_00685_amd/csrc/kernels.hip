@@ -75,35 +75,47 @@ __device__ inline uint8_t fp8_e4m3_rne(float x) {
 // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
 // XCD receives one contiguous run of the tile order (its L2 then holds the
 // operand panels that run shares).
+// A value known to be equal in all lanes, moved to scalar registers.
+__device__ inline int64_t uniform64(int64_t v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
     const int64_t per = nb / 8, rem = nb % 8;
     const int64_t x = b % 8, s = b / 8;
     return x * per + (x < rem ? x : rem) + s;
 }
 
-// Upper-triangle tile order, grouped by G column tiles: group g covers
-// columns [gG, gG+G); inside it, rows 0..gG-1 take the full group width, then
-// the group's own triangle.  Tiles that run together share a few row panels
-// and one group of column panels.
-__device__ inline void decode_upper(int64_t t, int T, int G, int& I, int& J) {
-    int g = 0;
-    for (;; ++g) {
-        const int gw = min(G, T - g * G);
-        const int64_t cnt = (int64_t)g * G * gw + (int64_t)gw * (gw + 1) / 2;
+// Upper-triangle tile order for tiles R times as tall as they are wide
+// (row tile I covers rows [I*R*w, (I+1)*R*w) for column tiles of width w, so
+// tile (I, J) holds an element with j >= i exactly when J >= R*I).  Tiles
+// are grouped by G column tiles: group g covers column tiles [gG, gG+G);
+// inside it the row tiles follow one another, each taking the columns of the
+// group that lie on or above the diagonal.  Tiles that run together share a
+// few row panels and one group of column panels.
+__host__ __device__ inline void decode_upper(int64_t t, int TI, int TJ, int R, int G, int& I, int& J) {
+    int c0 = 0, c1 = 0, nfull = 0;
+    for (c0 = 0;; c0 += G) {
+        c1 = c0 + G < TJ ? c0 + G : TJ;
+        nfull = c0 / R + 1 < TI ? c0 / R + 1 : TI;   // rows whose diagonal lies left of the group
+        int64_t cnt = (int64_t)nfull * (c1 - c0);
+        for (int r = nfull; r < TI && R * r < c1; ++r) cnt += c1 - R * r;
         if (t < cnt) break;
         t -= cnt;
     }
-    const int gG = g * G, gw = min(G, T - gG);
-    if (t < (int64_t)gG * gw) {
+    const int gw = c1 - c0;
+    if (t < (int64_t)nfull * gw) {
         I = (int)(t / gw);
-        J = gG + (int)(t % gw);
+        J = c0 + (int)(t % gw);
         return;
     }
-    t -= (int64_t)gG * gw;
-    int r = 0;
-    while (t >= gw - r) { t -= gw - r; ++r; }
-    I = gG + r;
-    J = gG + r + (int)t;
+    t -= (int64_t)nfull * gw;
+    int r = nfull;
+    while (t >= c1 - R * r) { t -= c1 - R * r; ++r; }
+    I = r;
+    J = R * r + (int)t;
 }
 
 // Full-grid tile order for heterocorrelation, grouped by G column tiles.
@@ -763,18 +775,43 @@ __device__ inline void mma32(f16v& acc, const typename Wide<P>::T& a, const type
     else acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
 }
 
-constexpr int kStages = 3;
-template <int P> constexpr int stage_bytes() { return 3 * planes(P) * 4096; }
+// Tiles of the LDS-staged contraction: TM output rows (128 or 256) x 128
+// output columns, TM/32 waves, each wave a 64 x 64 block of Phi and of Psi
+// (2 x 2 blocks of the 32 x 32 MFMA).  One K stage (16 contraction elements)
+// per plane holds the TM/128 panels of the left operand and one panel of
+// each right operand (4 KB each), copied straight from the panel-blocked
+// layout.  TM = 256 runs one 8-wave workgroup per CU; TM = 128 two 4-wave
+// workgroups, so that one's epilogue can overlap the other's K loop.
+constexpr int kTileN2 = 128;
+constexpr int threads2(int TM) { return TM * 2; }
+template <int P, int TM> constexpr int stage_bytes() { return planes(P) * (TM * 32 + 8192); }
+// Stages in the ring: 128 KB for TM = 256 (one workgroup per CU), 72 KB for
+// TM = 128 (two per CU).
+template <int P, int TM> constexpr int ring_stages() {
+    return TM == 256 ? (planes(P) == 2 ? 4 : 8) : (planes(P) == 2 ? 3 : 6);
+}
 constexpr int kOutPitch = 132;   // floats per row of the LDS output tile (128 + 4)
 // LDS of a contraction workgroup: the operand ring, reused by the output tile
-template <int P> constexpr int corr2_lds_bytes() {
-    return kStages * stage_bytes<P>() > 128 * kOutPitch * 4 ? kStages * stage_bytes<P>()
-                                                              : 128 * kOutPitch * 4;
+template <int P, int TM> constexpr int corr2_lds_bytes() {
+    return ring_stages<P, TM>() * stage_bytes<P, TM>() > TM * kOutPitch * 4
+               ? ring_stages<P, TM>() * stage_bytes<P, TM>()
+               : TM * kOutPitch * 4;
 }
 
 template <int N>
 __device__ inline void wait_vmcnt() {
     asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+// Wait until at most `ahead` stages of OPSW loads each are outstanding
+// (vector memory operations of one wave complete in issue order).
+template <int OPSW, int MAXA>
+__device__ inline void wait_stages(int ahead) {
+    if constexpr (MAXA == 0) {
+        wait_vmcnt<0>();
+    } else {
+        if (ahead >= MAXA) wait_vmcnt<OPSW * MAXA>();
+        else wait_stages<OPSW, MAXA - 1>(ahead);
+    }
 }
 __device__ inline void lds_barrier() {
     asm volatile("" ::: "memory");
@@ -789,14 +826,23 @@ __device__ inline void lds_write_barrier() {
     asm volatile("" ::: "memory");
 }
 
-// Epilogue of one 128 x 128 output tile of Phi (psi = false) or Psi.
-// The waves normalize their accumulators in FP64 (x c / (sL_i sR_j)), round
-// once to the output type and write them into an LDS tile (the operand ring
-// is free by then); all 256 threads then store rows of the tile as
+// Epilogue of one TM x 128 output tile of Phi (psi = false) or Psi.
+// The waves normalize their accumulators in FP64 by the column factor
+// c / sR_j, round once to FP32 and write them into an LDS tile (the operand
+// ring is free by then); all threads then store rows of the tile as
 // contiguous runs: 16-byte stores where the destination allows, the mirror
-// of a FULL homocorrelation read transposed from the same tile.  Accumulator
-// register r of lane l holds row 8(r/4) + 4(l/32) + r%4 and column l%32 of
-// its 32 x 32 block.
+// of a FULL homocorrelation read transposed from the same tile.  The row
+// scale 1 / sL_i (a power of two) is applied exactly with ldexp as the
+// rows leave LDS; this equals the single FP64 product unless the result is
+// an FP32 subnormal.  Accumulator register r of lane l holds row
+// 8(r/4) + 4(l/32) + r%4 and column l%32 of its 32 x 32 block.
+
+// Exponent of a power-of-two scale.
+__device__ inline int pow2_exp(float s) { return ((__float_as_int(s) >> 23) & 0xff) - 127; }
+__device__ inline float4 row_unscale(float4 v, float s) {
+    const int e = -pow2_exp(s);
+    return make_float4(ldexpf(v.x, e), ldexpf(v.y, e), ldexpf(v.z, e), ldexpf(v.w, e));
+}
 
 __device__ inline void put4(void* base, int64_t idx, float4 v, bool f64, bool aligned) {
     if (f64) {
@@ -818,43 +864,49 @@ __device__ inline void put1(void* base, int64_t idx, float v, bool f64) {
     else ((float*)base)[idx] = v;
 }
 
+template <int TM>
 __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][2], char* lds, bool psi) {
+    constexpr int NT = threads2(TM);
     float* T = (float*)lds;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // opaque copy of the thread index: keeps the index arithmetic below
+    // inside a persistent tile loop instead of hoisted and spilled
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1, g = lane >> 5;
     const bool homo = C.homo;
-    const bool diag = homo && I == J;
+    const int64_t i0 = (int64_t)I * TM, j0 = (int64_t)J * kTileN2;
+    // homocorrelation tiles that reach down to the diagonal (j <= i somewhere)
+    const bool diag = homo && j0 <= i0 + TM - 1;
     lds_barrier();   // previous readers of the LDS are done
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const int jl = wj * 64 + b * 32 + (lane & 31);
         double fc = C.c;
-        if (C.scaled) fc *= inv_pow2(psi ? C.sRB[(int64_t)J * 128 + jl] : C.sRA[(int64_t)J * 128 + jl]);
+        if (C.scaled) fc *= inv_pow2(psi ? C.sRB[j0 + jl] : C.sRA[j0 + jl]);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int il = wi * 64 + a * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-                double f = fc;
-                if (C.scaled) f *= inv_pow2(C.sL[(int64_t)I * 128 + il]);
-                float v = (float)((double)acc[a][b][r] * f);
-                if (psi && diag && il == jl) v = 0.0f;
+                float v = (float)((double)acc[a][b][r] * fc);
+                if (psi && diag && i0 + il == j0 + jl) v = 0.0f;
                 T[il * kOutPitch + jl] = v;
             }
     }
     lds_write_barrier();
     void* out = psi ? C.psi : C.phi;
     const bool f64 = C.out_f64;
-    const int cl = (threadIdx.x & 31) * 4;   // 4 consecutive columns per thread
-    const int rsub = threadIdx.x >> 5;        // 8 rows per pass
-    const int64_t i0 = (int64_t)I * 128, j0 = (int64_t)J * 128;
-    const bool inside = i0 + 128 <= C.n1 && j0 + 128 <= C.n2;
-    for (int pass = 0; pass < 16; ++pass) {
-        const int rl = pass * 8 + rsub;
-        const int64_t i = i0 + rl, j = j0 + cl;
-        const float4 v = *(const float4*)(T + rl * kOutPitch + cl);
-        if (!homo || C.layout == L_FULL) {
-            // direct rows (homo: the upper part; diagonal tiles mask i > j)
+    const bool inside = i0 + TM <= C.n1 && j0 + kTileN2 <= C.n2;
+    if (!homo || C.layout == L_FULL) {
+        // direct rows (homo: the upper part; diagonal tiles mask j < i)
+        const int cl = (tid & 31) * 4;   // 4 consecutive columns per thread
+        const int rsub = tid >> 5;        // NT / 32 rows per pass
+        for (int pass = 0; pass < TM / (NT / 32); ++pass) {
+            const int rl = pass * (NT / 32) + rsub;
+            const int64_t i = i0 + rl, j = j0 + cl;
+            float4 v = *(const float4*)(T + rl * kOutPitch + cl);
+            if (C.scaled) v = row_unscale(v, C.sL[i]);
             const int64_t idx = i * C.ld_out + j;
             if (inside && !diag) {
                 put4(out, idx, v, f64, ((idx & 3) == 0) && ((C.ld_out & 3) == 0));
@@ -868,13 +920,25 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
                     put1(out, idx + q, e[q], f64);
                 }
             }
-            if (homo) {
-                // mirror tile (J, I): row jm = j0 + rl, columns i0 + cl..+3,
-                // value -(+)T[c][rl] for Psi (Phi); diagonal tiles fill i > j
-                const int64_t jm = j0 + rl, im = i0 + cl;
-                const float sg = psi ? -1.0f : 1.0f;
-                const float4 t = make_float4(sg * T[(cl + 0) * kOutPitch + rl], sg * T[(cl + 1) * kOutPitch + rl],
-                                             sg * T[(cl + 2) * kOutPitch + rl], sg * T[(cl + 3) * kOutPitch + rl]);
+        }
+        if (homo) {
+            // mirror: row jm = j0 + rr, columns i0 + cc..cc+3 take -(+)T[cc+q][rr]
+            // for Psi (Phi); diagonal tiles write only the strictly lower part
+            const int cc = (tid % (TM / 4)) * 4;   // TM / 4 threads x 4 columns
+            const int rsub8 = tid / (TM / 4);      // 8 rows per pass
+            const float sg = psi ? -1.0f : 1.0f;
+            // rows i0 + cc .. cc+3 of the tile are this thread's mirror columns
+            int er[4] = {0, 0, 0, 0};
+            if (C.scaled)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) er[q] = -pow2_exp(C.sL[i0 + cc + q]);
+            for (int pass = 0; pass < kTileN2 / 8; ++pass) {
+                const int rr = pass * 8 + rsub8;
+                const int64_t jm = j0 + rr, im = i0 + cc;
+                const float4 t = make_float4(ldexpf(sg * T[(cc + 0) * kOutPitch + rr], er[0]),
+                                             ldexpf(sg * T[(cc + 1) * kOutPitch + rr], er[1]),
+                                             ldexpf(sg * T[(cc + 2) * kOutPitch + rr], er[2]),
+                                             ldexpf(sg * T[(cc + 3) * kOutPitch + rr], er[3]));
                 const int64_t midx = jm * C.ld_out + im;
                 if (inside && !diag) {
                     put4(out, midx, t, f64, ((midx & 3) == 0) && ((C.ld_out & 3) == 0));
@@ -889,53 +953,83 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
                     }
                 }
             }
-        } else {
-            // UPPER_PACKED: element (i, j) at rowbase(i) + j, j >= i
-            if (i < C.n1) {
-                const int64_t idx = packed_row_base(i, C.n1) + j;
-                if (inside && !diag) {
-                    put4(out, idx, v, f64, (idx & 3) == 0);
-                } else {
-                    const float e[4] = {v.x, v.y, v.z, v.w};
+        }
+    } else {
+        // UPPER_PACKED: element (i, j) at rowbase(i) + j, j >= i
+        const int cl = (tid & 31) * 4;
+        const int rsub = tid >> 5;
+        for (int pass = 0; pass < TM / (NT / 32); ++pass) {
+            const int rl = pass * (NT / 32) + rsub;
+            const int64_t i = i0 + rl, j = j0 + cl;
+            if (i >= C.n1) break;
+            float4 v = *(const float4*)(T + rl * kOutPitch + cl);
+            if (C.scaled) v = row_unscale(v, C.sL[i]);
+            const int64_t idx = packed_row_base(i, C.n1) + j;
+            if (inside && !diag) {
+                put4(out, idx, v, f64, (idx & 3) == 0);
+            } else {
+                const float e[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int64_t jj = j + q;
-                        if (jj >= C.n2) break;
-                        if (jj < i) continue;
-                        put1(out, idx + q, e[q], f64);
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t jj = j + q;
+                    if (jj >= C.n2) break;
+                    if (jj < i) continue;
+                    put1(out, idx + q, e[q], f64);
                 }
             }
         }
     }
 }
 
-template <int P>
+// One TM x 128 output tile: the K loop over a ring of LDS stages filled by
+// direct-to-LDS loads, then the epilogue.  A plane's stage is CH = TM/32 + 8
+// chunks of 1 KB: chunks 0..TM/32-1 hold the left panels, then 4 for the
+// synchronous right panel and 4 for the asynchronous one; wave w copies
+// chunks w, w + NW, ... of every plane.
+template <int P, int TM>
 __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
     using FT = typename Wide<P>::T;
     constexpr int PL = planes(P);
-    constexpr int OPS = 3 * PL;          // operand planes per stage: (L, RA, RB) x planes
-    constexpr int SB = stage_bytes<P>();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int S = ring_stages<P, TM>();
+    constexpr int SB = stage_bytes<P, TM>();
+    constexpr int NW = TM / 32;          // waves
+    constexpr int CH = TM / 32 + 8;      // 1 KB chunks per plane and stage
+    constexpr int CPW = CH / NW;         // chunks per wave and plane
+    constexpr int PB = TM * 32 + 8192;   // plane bytes per stage
+    constexpr int OPSW = CPW * PL;       // loads per wave per stage
+    // opaque copy of the thread index: in a persistent tile loop the values
+    // derived from it are then recomputed per tile rather than kept live
+    // (and spilled) across the epilogue
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1;
     const int nkb = C.kp >> 4;
+    const int64_t panel_bytes = (int64_t)nkb * 4096;
 
-    // global source of this wave's 1 KB part (rows w*32..w*32+31) of each
-    // plane's stage; stage kb of a panel is 4 KB after stage kb-1
-    const char* src[OPS];
+    const char* src[PL][CPW];
 #pragma unroll
-    for (int t = 0; t < OPS; ++t) {
-        const int which = t % 3, plane = t / 3;
-        const void* b = which == 0 ? (plane ? C.L1 : C.L0)
-                                   : which == 1 ? (plane ? C.RA1 : C.RA0) : (plane ? C.RB1 : C.RB0);
-        const int64_t panel = which == 0 ? (int64_t)I : (int64_t)J;
-        src[t] = (const char*)b + panel * nkb * 4096 + w * 1024 + lane * 16;
-    }
+    for (int p = 0; p < PL; ++p)
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            const int c = w + k * NW;
+            const char* b;
+            if (c < TM / 32) {
+                b = (const char*)(p ? C.L1 : C.L0) + ((int64_t)I * (TM / 128) + (c >> 2)) * panel_bytes;
+            } else {
+                const int r = c - TM / 32;
+                b = (const char*)(r < 4 ? (p ? C.RA1 : C.RA0) : (p ? C.RB1 : C.RB0)) + (int64_t)J * panel_bytes;
+            }
+            src[p][k] = b + (c & 3) * 1024 + lane * 16;
+        }
     auto issue = [&](int kb) {
-        char* dst = lds + (kb % kStages) * SB + w * 1024;
+        char* dst = lds + (kb % S) * SB;
 #pragma unroll
-        for (int t = 0; t < OPS; ++t)
-            __builtin_amdgcn_global_load_lds(AS_GLOBAL(src[t] + kb * 4096), AS_LDS(dst + t * 4096), 16, 0, 0);
+        for (int p = 0; p < PL; ++p)
+#pragma unroll
+            for (int k = 0; k < CPW; ++k)
+                __builtin_amdgcn_global_load_lds(AS_GLOBAL(src[p][k] + kb * 4096),
+                                                 AS_LDS(dst + p * PB + (w + k * NW) * 1024), 16, 0, 0);
     };
 
     // LDS byte offsets of this lane's fragment rows (K-block half g = lane/32)
@@ -946,7 +1040,7 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
         const int ra = wi * 64 + a * 32 + (lane & 31);
         const int rb = wj * 64 + a * 32 + (lane & 31);
         offA[a] = ra * 32 + ((g ^ row_swizzle(ra)) << 4);
-        offB[a] = rb * 32 + ((g ^ row_swizzle(rb)) << 4);
+        offB[a] = TM * 32 + rb * 32 + ((g ^ row_swizzle(rb)) << 4);
     }
 
     f16v ap[2][2], aq[2][2];
@@ -958,65 +1052,101 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
             aq[a][b] = f16v{};
         }
 
-    lds_barrier();   // the ring is free (previous tile of a persistent loop)
-    issue(0);
-    if (nkb > 1) issue(1);
-    for (int kb = 0; kb < nkb; ++kb) {
-        if (kb + 1 < nkb) wait_vmcnt<OPS>();
-        else wait_vmcnt<0>();
-        lds_barrier();
-        if (kb + 2 < nkb) issue(kb + 2);
-        const char* st = lds + (kb % kStages) * SB;
+    // Fragments of one stage, held in registers: the K loop reads stage kb+1
+    // from LDS while the MFMAs of stage kb run (two register sets).
+    struct Frags {
         FT la[PL][2], ra[PL][2], rb[PL][2];
+    };
+    auto load_frags = [&](Frags& F, int kb) {
+        const char* st = lds + (kb % S) * SB;
 #pragma unroll
         for (int p = 0; p < PL; ++p)
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                la[p][a] = *(const FT*)(st + (3 * p + 0) * 4096 + offA[a]);
-                ra[p][a] = *(const FT*)(st + (3 * p + 1) * 4096 + offB[a]);
-                rb[p][a] = *(const FT*)(st + (3 * p + 2) * 4096 + offB[a]);
+                F.la[p][a] = *(const FT*)(st + p * PB + offA[a]);
+                F.ra[p][a] = *(const FT*)(st + p * PB + offB[a]);
+                F.rb[p][a] = *(const FT*)(st + p * PB + 4096 + offB[a]);
             }
+    };
+    // MFMAs of one stage for the 32-row block a of the wave's 64 rows
+    auto mfma_rows = [&](const Frags& F, int a) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                mma32<P>(ap[a][b], la[0][a], ra[0][b]);
-                mma32<P>(aq[a][b], la[0][a], rb[0][b]);
-                if constexpr (PL == 2) {
-                    mma32<P>(ap[a][b], la[0][a], ra[1][b]);
-                    mma32<P>(aq[a][b], la[0][a], rb[1][b]);
-                    mma32<P>(ap[a][b], la[1][a], ra[0][b]);
-                    mma32<P>(aq[a][b], la[1][a], rb[0][b]);
-                }
+        for (int b = 0; b < 2; ++b) {
+            mma32<P>(ap[a][b], F.la[0][a], F.ra[0][b]);
+            mma32<P>(aq[a][b], F.la[0][a], F.rb[0][b]);
+            if constexpr (PL == 2) {
+                mma32<P>(ap[a][b], F.la[0][a], F.ra[1][b]);
+                mma32<P>(aq[a][b], F.la[0][a], F.rb[1][b]);
+                mma32<P>(ap[a][b], F.la[1][a], F.ra[0][b]);
+                mma32<P>(aq[a][b], F.la[1][a], F.rb[0][b]);
             }
+        }
+    };
+    // Stage kb+1 always exists where this runs (the number of K blocks is
+    // even), so the fragment reads are unconditional and the compiler waits
+    // for them only before the next step's MFMAs.
+    // The next stage's reads go between the two halves of the MFMAs: the
+    // wait for this stage's fragments comes before the first half, and the
+    // second half (and the next barrier) hide the new reads' latency.
+    auto step = [&](Frags& Fc, Frags& Fn, int kb) {
+        wait_stages<OPSW, S - 3>(min(S - 3, nkb - 2 - kb));
+        lds_barrier();
+        if (kb + S - 1 < nkb) issue(kb + S - 1);
+        mfma_rows(Fc, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_frags(Fn, kb + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_rows(Fc, 1);
+    };
+
+    lds_barrier();   // the ring is free (previous tile of a persistent loop)
+#pragma unroll
+    for (int st = 0; st < S - 1; ++st)
+        if (st < nkb) issue(st);
+    wait_stages<OPSW, S - 2>(min(S - 2, nkb - 1));
+    lds_barrier();
+    Frags F0, F1;
+    load_frags(F0, 0);
+    // nkb is even and at least 2: pairs of steps, then the last pair, whose
+    // second stage needs no further load (every load has landed and is
+    // visible after the last step's barrier)
+    for (int kb = 0; kb + 2 < nkb; kb += 2) {
+        step(F0, F1, kb);
+        step(F1, F0, kb + 1);
     }
+    step(F0, F1, nkb - 2);
+    mfma_rows(F1, 0);
+    mfma_rows(F1, 1);
 
     // epilogue through LDS, one output at a time
-    stage_out(C, I, J, ap, lds, false);
-    stage_out(C, I, J, aq, lds, true);
+    stage_out<TM>(C, I, J, ap, lds, false);
+    stage_out<TM>(C, I, J, aq, lds, true);
 }
 
-template <int P>
-__global__ __launch_bounds__(256, 2) void corr2_kernel(CorrJob C) {
-    __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P>()];
+template <int P, int TM>
+__global__ __launch_bounds__(threads2(TM), 512 / TM) void corr2_kernel(CorrJob C) {
+    __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
-    if (C.homo) decode_upper(t, C.tiles_i, C.group, I, J);
+    if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
     else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
-    corr2_tile<P>(C, I, J, lds);
+    corr2_tile<P, TM>(C, I, J, lds);
 }
 
-template <int P>
-__global__ __launch_bounds__(256, 2) void corr2_persistent_kernel(const CorrJob* jobs,
-                                                                   const int64_t* tile_start,
-                                                                   int count, int64_t total,
-                                                                   int* counter) {
-    __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P>()];
+template <int P, int TM>
+__global__ __launch_bounds__(threads2(TM), 512 / TM) void corr2_persistent_kernel(const CorrJob* jobs,
+                                                                       const int64_t* tile_start,
+                                                                       int count, int64_t total,
+                                                                       int* counter) {
+    __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
     __shared__ int64_t s_t;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
         __syncthreads();
-        const int64_t t = s_t;
+        // the ticket is the same for the whole workgroup: move it to scalar
+        // registers so that the job, its pointers and the tile indices are
+        // scalar values too
+        const int64_t t = uniform64(s_t);
         __syncthreads();
         if (t >= total) break;
         int lo = 0, hi = count - 1;
@@ -1027,8 +1157,8 @@ __global__ __launch_bounds__(256, 2) void corr2_persistent_kernel(const CorrJob*
         }
         const CorrJob C = jobs[lo];
         int I, J;
-        decode_upper(t - tile_start[lo], C.tiles_i, C.group, I, J);
-        corr2_tile<P>(C, I, J, lds);
+        decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
+        corr2_tile<P, TM>(C, I, J, lds);
     }
 }
 
@@ -1036,7 +1166,7 @@ template <int P, int FM, int FN>
 __global__ __launch_bounds__(256) void corr_kernel(CorrJob C) {
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
-    if (C.homo) decode_upper(t, C.tiles_i, C.group, I, J);
+    if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
     else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
     corr_tile<P, FM, FN>(C, I, J);
 }
@@ -1063,7 +1193,7 @@ __global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* job
         }
         const CorrJob C = jobs[lo];
         int I, J;
-        decode_upper(t - tile_start[lo], C.tiles_i, C.group, I, J);
+        decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
         corr_tile<P, FM, FN>(C, I, J);
     }
 }
@@ -1113,8 +1243,9 @@ hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipSt
 
 hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s) {
 #define Y(PP)                                                                                 \
-    if (prec == PP && fm == 4 && fn == 4) {                                                   \
-        hipLaunchKernelGGL((corr2_kernel<PP>), dim3((unsigned)blocks), dim3(256), 0, s, C);   \
+    if (prec == PP && (fm == 8 || fm == 4) && fn == 4) {                                      \
+        if (fm == 8) hipLaunchKernelGGL((corr2_kernel<PP, 256>), dim3((unsigned)blocks), dim3(512), 0, s, C); \
+        else hipLaunchKernelGGL((corr2_kernel<PP, 128>), dim3((unsigned)blocks), dim3(256), 0, s, C); \
         return hipGetLastError();                                                             \
     }
     CORR2_CASES(Y)
@@ -1133,9 +1264,13 @@ hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
                                   const int64_t* tile_start, int count, int64_t total,
                                   int* counter, int blocks, hipStream_t s) {
 #define Y(PP)                                                                                 \
-    if (prec == PP && fm == 4 && fn == 4) {                                                   \
-        hipLaunchKernelGGL((corr2_persistent_kernel<PP>), dim3(blocks), dim3(256), 0, s, jobs, \
-                           tile_start, count, total, counter);                                \
+    if (prec == PP && (fm == 8 || fm == 4) && fn == 4) {                                      \
+        if (fm == 8)                                                                          \
+            hipLaunchKernelGGL((corr2_persistent_kernel<PP, 256>), dim3(blocks), dim3(512), 0, s, jobs, \
+                               tile_start, count, total, counter);                            \
+        else                                                                                  \
+            hipLaunchKernelGGL((corr2_persistent_kernel<PP, 128>), dim3(blocks), dim3(256), 0, s, jobs, \
+                               tile_start, count, total, counter);                            \
         return hipGetLastError();                                                             \
     }
     CORR2_CASES(Y)
@@ -1152,7 +1287,7 @@ hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
 }
 
 int corr_variant_supported(int prec, int fm, int fn) {
-#define Y(PP) if (prec == PP && fm == 4 && fn == 4) return 1;
+#define Y(PP) if (prec == PP && (fm == 8 || fm == 4) && fn == 4) return 1;
     CORR2_CASES(Y)
 #undef Y
 #define X(PP, A, B) if (prec == PP && fm == A && fn == B) return 1;
@@ -1164,9 +1299,11 @@ int corr_variant_supported(int prec, int fm, int fn) {
 int persistent_blocks_per_cu(int prec, int fm, int fn) {
     int n = 0;
 #define Y(PP)                                                                             \
-    if (prec == PP && fm == 4 && fn == 4) {                                               \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr2_persistent_kernel<PP>, 256, 0) \
-            != hipSuccess) n = 1;                                                         \
+    if (prec == PP && (fm == 8 || fm == 4) && fn == 4) {                                  \
+        const hipError_t e = fm == 8                                                      \
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr2_persistent_kernel<PP, 256>, 512, 0) \
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr2_persistent_kernel<PP, 128>, 256, 0); \
+        if (e != hipSuccess) n = 1;                                                       \
         return n > 0 ? n : 1;                                                             \
     }
     CORR2_CASES(Y)

@@ -51,7 +51,7 @@ void load() {
         if (std::sscanf(line, "%d %lld %lld %d", &r.prec, &mm, &nn, &r.tile) == 4) {
             r.m_max = mm;
             r.n_max = nn;
-            if (r.tile == 1 || r.tile == 2) g_rules.push_back(r);
+            if (r.tile >= 1 && r.tile <= 3) g_rules.push_back(r);
         }
     }
     std::fclose(f);
@@ -64,11 +64,12 @@ int tune_lookup(int prec, int64_t m, int64_t n) {
     for (const Rule& r : g_rules)
         if (r.prec == prec && m <= r.m_max && n <= r.n_max) {
             if (prec == P_F64 && r.tile != 1) continue;
-            if (blocked_layout(prec) && r.tile != 2) continue;
+            if (blocked_layout(prec) && r.tile != 2 && r.tile != 3) continue;
+            if (!blocked_layout(prec) && r.tile == 3) continue;
             return r.tile;
         }
     if (prec == P_F64) return 1;
-    if (blocked_layout(prec)) return 2;
+    if (blocked_layout(prec)) return 3;
     return n <= 1024 ? 1 : 2;
 }
 

@@ -117,6 +117,8 @@ def _plan_status(**kw):
     (dict(flags=0x100), B.EINVAL),
     (dict(tile=7), B.EINVAL),
     (dict(prec=0, tile=2), B.EUNSUPPORTED),
+    (dict(prec=1, tile=3), B.EUNSUPPORTED),
+    (dict(prec=2, tile=3), B.OK),
     (dict(m=5000), B.EUNSUPPORTED),
     (dict(m=2, n1=1), B.OK),
     (dict(prec=5), B.OK),
@@ -147,8 +149,17 @@ def test_plan_info():
     _, h = B.corr2d_plan(d)
     info = B.corr2d_plan_get_info(h)
     assert info.k_pad == 256 and info.n_pad == 16384
-    assert info.tile_m == info.tile_n
+    # 16-bit formats: row tiles twice as tall as column tiles; the upper
+    # triangle holds the tiles (I, J) with J >= 2 I
+    assert (info.tile_m, info.tile_n) == (256, 128)
     t = 16384 // info.tile_m
+    assert info.tiles == sum(2 * t - 2 * i for i in range(t)) == t * (t + 1)
+    B.corr2d_plan_destroy(h)
+    d = B.corr2d_desc_init(m=256, n1=16384, prec="split_bf16", out_layout="upper_packed", tile=3)
+    _, h = B.corr2d_plan(d)
+    info = B.corr2d_plan_get_info(h)
+    assert (info.tile_m, info.tile_n) == (128, 128)
+    t = 16384 // 128
     assert info.tiles == t * (t + 1) // 2
     assert info.c == pytest.approx(1.0 / (256 * 255))
     B.corr2d_plan_destroy(h)

@@ -139,6 +139,35 @@ def test_upper_packed_layout(gpu, prec):
     assert np.all(np.diag(Q) == 0)
 
 
+@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
+@pytest.mark.parametrize("tile", [2, 3])
+@pytest.mark.parametrize("layout", ["full", "upper_packed"])
+def test_lds_staged_tile_shapes(gpu, prec, tile, layout):
+    # both tile shapes of the LDS-staged kernel (256 x 128 and 128 x 128),
+    # with ragged edges and several diagonal-crossing tiles
+    m, n = 37, 700
+    S = _rand(m, n, 77)
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, plan = _homo(S, gpu, prec=prec, layout=layout, tile=tile)
+    info = plan.info
+    assert (info.tile_m, info.tile_n) == ((256, 128) if tile == 2 else (128, 128))
+    if layout == "upper_packed":
+        phi, psi = unpack_upper(phi, n), unpack_upper(psi, n)
+        iu = np.triu_indices(n)
+        assert rel_fro(phi[iu], phi_o[iu]) <= TOL[prec]
+        assert rel_fro(psi[iu], psi_o[iu]) <= TOL[prec]
+        assert np.all(np.diag(psi) == 0)
+    else:
+        check_homo_structure(phi, psi)
+        assert rel_fro(phi, phi_o) <= TOL[prec]
+        assert rel_fro(psi, psi_o) <= TOL[prec]
+    S2 = _rand(m, 300, 78)
+    phi_o, psi_o = oracle.corr2d(S, S2)
+    phi, psi, _, _ = B.hetero(_t(S, gpu), _t(S2, gpu), prec=prec, tile=tile)
+    assert rel_fro(_np(phi), phi_o) <= TOL[prec]
+    assert rel_fro(_np(psi), psi_o) <= TOL[prec]
+
+
 # --------------------------------------------------------------------------
 # Heterocorrelation
 # --------------------------------------------------------------------------
