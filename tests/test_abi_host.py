@@ -145,11 +145,11 @@ def test_workspace_bytes_monotone_in_size():
 
 
 def test_plan_info():
-    d = B.corr2d_desc_init(m=256, n1=16384, prec="split_bf16", out_layout="upper_packed")
+    d = B.corr2d_desc_init(m=256, n1=16384, prec="split_bf16", out_layout="upper_packed", tile=2)
     _, h = B.corr2d_plan(d)
     info = B.corr2d_plan_get_info(h)
     assert info.k_pad == 256 and info.n_pad == 16384
-    # 16-bit formats: row tiles twice as tall as column tiles; the upper
+    # tile 2 of the 16-bit formats: row tiles twice as tall as column tiles; the upper
     # triangle holds the tiles (I, J) with J >= 2 I
     assert (info.tile_m, info.tile_n) == (256, 128)
     t = 16384 // info.tile_m
