@@ -16,7 +16,6 @@ the plain FP32, FP64 and BF16 forms, and the oracle timed on the host.
 from __future__ import annotations
 
 import argparse
-import ctypes
 import json
 import math
 import os
@@ -33,37 +32,6 @@ METRIC = ("correlation entries/s and MFMA TFLOP/s at stated error vs oracle; "
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "split_bf16": 2500.0, "bf16": 2500.0,
                "f16": 2500.0, "fp8_e4m3": 5000.0}
 HBM_GBPS = 8000.0
-
-
-class HipEvents:
-    """hipEvent_t handles through libamdhip64 (the library records them on
-    the stream its kernels run on)."""
-
-    def __init__(self):
-        self.h = ctypes.CDLL("libamdhip64.so")
-        self.h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
-        self.h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
-                                               ctypes.c_void_p]
-        self.h.hipEventDestroy.argtypes = [ctypes.c_void_p]
-        self.h.hipEventSynchronize.argtypes = [ctypes.c_void_p]
-
-    def create(self, n):
-        evs = []
-        for _ in range(n):
-            e = ctypes.c_void_p()
-            assert self.h.hipEventCreate(ctypes.byref(e)) == 0
-            evs.append(e.value)
-        return evs
-
-    def elapsed_ms(self, a, b):
-        self.h.hipEventSynchronize(b)
-        t = ctypes.c_float()
-        assert self.h.hipEventElapsedTime(ctypes.byref(t), a, b) == 0
-        return float(t.value)
-
-    def destroy(self, evs):
-        for e in evs:
-            self.h.hipEventDestroy(e)
 
 
 def sample_pairs(n, count, seed, centers):
@@ -156,27 +124,185 @@ def measured_traffic(kernel_tag="corr2_split_m256_n16384"):
 
 
 def cpu_baseline(oracle, S, target_s):
-    """The oracle's direct route on a bounded sample of output rows."""
+    """The oracle's direct route on a bounded sample of output rows: calls on
+    doubling row counts until one takes about a third of the target, then
+    one call sized to the target from that call's rate (reported)."""
     Y, _ = oracle.dynamic(S)
     m, n = Y.shape
-    # two short runs separate the per-row cost from the fixed cost (the
-    # Hilbert-Noda transform of all columns), then one run of ~target_s
-    times = {}
-    for r in (32, 128):
+    rows = 256
+    while True:
         t0 = time.perf_counter()
-        oracle.corr_ht(Y[:, :r], Y)
-        times[r] = time.perf_counter() - t0
-    per_row = max((times[128] - times[32]) / 96.0, 1e-6)
-    fixed = max(times[32] - 32 * per_row, 0.0)
-    rows = int(min(n, max(128, (target_s - fixed) / per_row)))
+        oracle.corr_ht(Y[:, :rows], Y)
+        dt = time.perf_counter() - t0
+        if dt >= target_s / 3 or rows >= n:
+            break
+        rows = min(n, rows * 2)
+    calls = 1
+    if rows < n:
+        rows = int(min(n, max(rows, rows * target_s / dt)))
+    else:
+        # the whole matrix is quicker than the target: repeat it
+        calls = max(1, int(round(target_s / max(dt, 1e-3))))
     t0 = time.perf_counter()
-    oracle.corr_ht(Y[:, :rows], Y)
+    for _ in range(calls):
+        oracle.corr_ht(Y[:, :rows], Y)
     dt = time.perf_counter() - t0
-    return {"value": rows * n / dt, "unit": "entries/s", "cores": oracle.threads(),
+    return {"value": calls * rows * n / dt, "unit": "entries/s", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"direct route (FP64, OpenMP) for the first {rows} spectral points "
-                      f"against all {n} of the m={m} x n={n} workload: {rows * n} "
-                      f"(Phi, Psi) entries in {dt:.1f} s"}
+                      f"against all {n} of the m={m} x n={n} workload, {calls} call(s): "
+                      f"{calls * rows * n} (Phi, Psi) entries in {dt:.1f} s"}
+
+
+def time_calls(torch, fn, reps):
+    """Wall time per call of `reps` back-to-back calls (ms)."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def kernel_ms(B, torch, plan, call, ev, reps=5):
+    """Mean contraction-kernel time (ms) through the library's timing hook."""
+    evs = ev.create(2 * reps)
+    for r in range(reps):
+        B.corr2d_plan_set_timing_events(plan.handle, evs[2 * r], evs[2 * r + 1])
+        call()
+    torch.cuda.synchronize()
+    ms = [ev.elapsed_ms(evs[2 * r], evs[2 * r + 1]) for r in range(reps)]
+    B.corr2d_plan_set_timing_events(plan.handle, None, None)
+    ev.destroy(evs)
+    return float(np.mean(ms))
+
+
+def other_workloads(B, torch, oracle, synth, ev, dev):
+    """The other workload configurations: small FP64 (latency), medium full
+    FP32/FP64 (output-bound), heterocorrelation FP16/FP8 (output-bound) and
+    the batch of 256 data sets (persistent graph against sequential
+    launches), each with its error against the oracle."""
+    out = []
+
+    # small: m = 11, n = 512, FP64, full output
+    S, _ = synth.workload_small()
+    m, n = S.shape
+    y = torch.as_tensor(S, device=dev)
+    plan = B.Plan(m=m, n1=n, n2=0, prec="f64", in_dtype="f64", out_dtype="f64")
+    phi = torch.empty(n * n, dtype=torch.float64, device=dev)
+    psi = torch.empty(n * n, dtype=torch.float64, device=dev)
+    ws = plan.workspace(dev)
+    call = lambda: B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
+    ms = time_calls(torch, call, 50)
+    po, qo = oracle.corr2d(S)
+    out.append({"workload": f"homocorrelation m={m} n={n}, FP64, full output", "prec": "f64",
+                "ms_per_call": ms, "entries_per_s": n * n / (ms * 1e-3),
+                "err_phi": rel_fro(phi.cpu().numpy().reshape(n, n), po),
+                "err_psi": rel_fro(psi.cpu().numpy().reshape(n, n), qo)})
+    del plan, phi, psi, ws
+
+    # medium: m = 64, n = 4096, FP32 and FP64, full output (mirror stored)
+    S, meta = synth.workload_medium()
+    m, n = S.shape
+    y = torch.as_tensor(S, device=dev)
+    si, sj = sample_pairs(n, 2000, 7, meta["centers"][:16])
+    po, qo = oracle.corr2d_entries(S, si, sj)
+    for prec in ("f32", "f64"):
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        plan = B.Plan(m=m, n1=n, n2=0, prec=prec, in_dtype="f64", out_dtype=prec)
+        phi = torch.empty(n * n, dtype=tdt, device=dev)
+        psi = torch.empty(n * n, dtype=tdt, device=dev)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
+        ms = time_calls(torch, call, 20)
+        kms = kernel_ms(B, torch, plan, call, ev)
+        idx = torch.as_tensor(si * n + sj, device=dev)
+        nbytes = 2 * n * n * (8 if prec == "f64" else 4)
+        out.append({"workload": f"homocorrelation m={m} n={n}, full output", "prec": prec,
+                    "ms_per_call": ms, "entries_per_s": n * n / (ms * 1e-3), "kernel_ms": kms,
+                    "roofline": {"bound": "hbm", "achieved": nbytes / (kms * 1e-3) / 1e9,
+                                 "peak": HBM_GBPS, "unit": "GB/s",
+                                 "frac": nbytes / (kms * 1e-3) / 1e9 / HBM_GBPS,
+                                 "bytes_per_launch": nbytes},
+                    "err_phi": rel_fro(phi[idx].double().cpu().numpy(), po),
+                    "err_psi": rel_fro(psi[idx].double().cpu().numpy(), qo)})
+        del plan, phi, psi, ws
+
+    # heterocorrelation: m = 128, n1 = 8192, n2 = 2048, FP16 and FP8, full output
+    S1, S2, meta = synth.workload_hetero()
+    m, n1 = S1.shape
+    n2 = S2.shape[1]
+    y1 = torch.as_tensor(S1, device=dev)
+    y2 = torch.as_tensor(S2, device=dev)
+    rng = np.random.default_rng(9)
+    hi, hj = rng.integers(0, n1, 3000), rng.integers(0, n2, 3000)
+    po, qo = oracle.corr2d_entries(S1, hi, hj, S2=S2)
+    for prec in ("f16", "fp8_e4m3"):
+        plan = B.Plan(m=m, n1=n1, n2=n2, prec=prec, in_dtype="f64", out_dtype="f32")
+        phi = torch.empty(n1 * n2, dtype=torch.float32, device=dev)
+        psi = torch.empty(n1 * n2, dtype=torch.float32, device=dev)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_hetero(plan.handle, y1, None, y2, None, phi, psi, ws)
+        ms = time_calls(torch, call, 20)
+        kms = kernel_ms(B, torch, plan, call, ev)
+        idx = torch.as_tensor(hi * n2 + hj, device=dev)
+        nbytes = 2 * n1 * n2 * 4
+        out.append({"workload": f"heterocorrelation m={m} n1={n1} n2={n2}, full output",
+                    "prec": prec, "ms_per_call": ms, "entries_per_s": n1 * n2 / (ms * 1e-3),
+                    "kernel_ms": kms,
+                    "roofline": {"bound": "hbm", "achieved": nbytes / (kms * 1e-3) / 1e9,
+                                 "peak": HBM_GBPS, "unit": "GB/s",
+                                 "frac": nbytes / (kms * 1e-3) / 1e9 / HBM_GBPS,
+                                 "bytes_per_launch": nbytes},
+                    "err_phi": rel_fro(phi[idx].double().cpu().numpy(), po),
+                    "err_psi": rel_fro(psi[idx].double().cpu().numpy(), qo)})
+        del plan, phi, psi, ws
+
+    # batch of 256 data sets, FP32, upper triangles
+    items = synth.batch_spec()
+    data = [synth.batch_item_data(it) for it in items]
+    offs, ooffs, cur, ocur = [], [], 0, 0
+    for it in items:
+        offs.append(cur)
+        ooffs.append(ocur)
+        cur += it.m * it.n
+        ocur += it.n * (it.n + 1) // 2
+    y = torch.empty(cur, dtype=torch.float64, device=dev)
+    for it, Sd, o in zip(items, data, offs):
+        y[o:o + it.m * it.n] = torch.as_tensor(Sd.ravel(), device=dev)
+    phi = torch.empty(ocur, dtype=torch.float32, device=dev)
+    psi = torch.empty(ocur, dtype=torch.float32, device=dev)
+    spec = [(it.m, it.n, o, 0, oo) for it, o, oo in zip(items, offs, ooffs)]
+    res = {}
+    for name, flags in (("graph", 0), ("sequential", B.FLAG_SEQUENTIAL)):
+        plan = B.Plan(B.corr2d_desc_init(prec="f32", out_layout="upper_packed", flags=flags),
+                      items=spec)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_batched(plan.handle, y, phi, psi, ws)
+        res[name] = time_calls(torch, call, 5)
+        if name == "graph":
+            gp = phi.double().cpu().numpy()
+            gq = psi.double().cpu().numpy()
+        del plan, ws
+    errs_p, errs_q = [], []
+    for k in range(0, len(items), 32):
+        it, Sd, oo = items[k], data[k], ooffs[k]
+        i, j = sample_pairs(it.n, 200, 100 + k, [])
+        pe, qe = oracle.corr2d_entries(Sd, i, j)
+        pidx = oo + i * it.n - (i * (i - 1)) // 2 + (j - i)
+        errs_p.append(rel_fro(gp[pidx], pe))
+        errs_q.append(rel_fro(gq[pidx], qe))
+    entries = sum(it.n * (it.n + 1) // 2 for it in items)
+    out.append({"workload": f"batch of {len(items)} homocorrelations, m in 8..200, n in 256..8192, "
+                            "FP32, upper triangles",
+                "prec": "f32", "ms_per_call": res["graph"], "entries_per_s": entries / (res["graph"] * 1e-3),
+                "sequential_ms_per_call": res["sequential"],
+                "graph_speedup": res["sequential"] / res["graph"],
+                "err_phi": max(errs_p), "err_psi": max(errs_q)})
+    del phi, psi, y
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -186,8 +312,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variant-steps", type=int, default=5)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--m", type=int, default=256)
     ap.add_argument("--n", type=int, default=16384)
     args = ap.parse_args()
@@ -203,6 +330,7 @@ def main():
     import oracle
     from paper_1808_00685_amd import binding as B
     from paper_1808_00685_amd import synth
+    from paper_1808_00685_amd.timing import HipEvents
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.lib()  # fail loudly if the HIP library is missing
@@ -223,6 +351,10 @@ def main():
                             ("f64", "fourier")):
             variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, sample,
                                         oracle_vals))
+
+    workloads = []
+    if not args.no_workloads:
+        workloads = other_workloads(B, torch, oracle, synth, ev, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -266,6 +398,7 @@ def main():
         "variants": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()
                       if k not in ("alg_flops", "executed_flops", "kernel_bytes")}
                      for r in variants],
+        "workloads": workloads,
     }
     print(json.dumps(line), flush=True)
 

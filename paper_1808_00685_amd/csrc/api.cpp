@@ -119,7 +119,14 @@ struct corr2d_plan_s {
         int64_t ntiles;
     };
     std::vector<Item> items;
-    std::vector<int> order;             // items in descending cost
+    std::vector<int> order;             // items by tile shape, then in descending cost
+    // one persistent launch per tile shape: items order[first, first + count)
+    struct Group {
+        Tile tile;
+        int first = 0, count = 0;
+        int64_t tiles = 0;
+    };
+    std::vector<Group> groups;
     std::vector<int64_t> distinct_m;
     std::vector<size_t> table_of_m;
     size_t jobs_off = 0, jobs_bytes = 0;
@@ -447,19 +454,6 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
     p->batched = true;
     set_scaling(p);
     const bool t64 = common->prec == CORR2D_PREC_F64;
-    // one tile shape for the whole persistent launch: the tuned choice for the
-    // median data set
-    std::vector<int64_t> ns;
-    for (int64_t i = 0; i < count; ++i) ns.push_back(items[i].n);
-    std::sort(ns.begin(), ns.end());
-    std::vector<int64_t> msv;
-    for (int64_t i = 0; i < count; ++i) msv.push_back(items[i].m);
-    std::sort(msv.begin(), msv.end());
-    p->tile = choose_tile(common, msv[count / 2], ns[count / 2]);
-    if (!corr_variant_supported(common->prec, p->tile.fm, p->tile.fn)) {
-        delete p;
-        return fail(CORR2D_EUNSUPPORTED, "tile %d is not built for precision %d", p->tile.id, common->prec);
-    }
     size_t off = 0;
     // tables per distinct m
     for (int64_t i = 0; i < count; ++i) {
@@ -481,22 +475,46 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
         const size_t mi = std::find(p->distinct_m.begin(), p->distinct_m.end(), I.it.m) - p->distinct_m.begin();
         I.table_off = p->table_of_m[mi];
         I.c = contraction_factor(common, I.it.m);
-        I.tile = p->tile;
-        I.ntiles = triangle_tiles(I.g.n_pad / (32 * p->tile.fm), p->tile.fm / p->tile.fn);
+        // each data set takes the tuned tile shape for its own m and n
+        I.tile = choose_tile(common, I.it.m, I.it.n);
+        if (!corr_variant_supported(common->prec, I.tile.fm, I.tile.fn)) {
+            delete p;
+            return fail(CORR2D_EUNSUPPORTED, "tile %d is not built for precision %d", I.tile.id, common->prec);
+        }
+        I.ntiles = triangle_tiles(I.g.n_pad / (32 * I.tile.fm), I.tile.fm / I.tile.fn);
         const int64_t outn = common->out_layout == CORR2D_LAYOUT_UPPER_PACKED
                                  ? I.it.n * (I.it.n + 1) / 2 : I.it.n * I.it.n;
         p->out_elements = std::max(p->out_elements, I.it.out_offset + outn);
     }
-    // descending cost order (longest processing time first)
+    // grouped by tile shape, each group in descending cost order (longest
+    // processing time first)
     p->order.resize(count);
     for (int64_t i = 0; i < count; ++i) p->order[i] = (int)i;
     std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
         const auto& A = p->items[a];
         const auto& B = p->items[b];
-        return (double)A.g.kp * A.ntiles > (double)B.g.kp * B.ntiles;
+        if (A.tile.id != B.tile.id) return A.tile.id < B.tile.id;
+        return (double)A.g.kp * A.ntiles * A.tile.fm * A.tile.fn >
+               (double)B.g.kp * B.ntiles * B.tile.fm * B.tile.fn;
     });
     p->total_tiles = 0;
     for (auto& I : p->items) p->total_tiles += I.ntiles;
+    for (int64_t r = 0; r < count; ++r) {
+        const auto& I = p->items[p->order[r]];
+        if (p->groups.empty() || p->groups.back().tile.id != I.tile.id) {
+            corr2d_plan_s::Group gr;
+            gr.tile = I.tile;
+            gr.first = (int)r;
+            p->groups.push_back(gr);
+        }
+        p->groups.back().count += 1;
+        p->groups.back().tiles += I.ntiles;
+    }
+    // the plan reports the shape that covers the most output tiles
+    p->tile = p->groups[0].tile;
+    int64_t best = -1;
+    for (const auto& gr : p->groups)
+        if (gr.tiles > best) { best = gr.tiles; p->tile = gr.tile; }
     // job arrays: tables, prep, corr, block starts, tile starts
     const size_t nd = p->distinct_m.size();
     p->jobs_bytes = align256(nd * sizeof(TableJob)) + align256((nd + 1) * sizeof(int32_t)) +
@@ -690,6 +708,9 @@ void fill_blob(corr2d_plan_s* p, const void* y_base, void* phi_base, void* psi_b
     int64_t tt = 0;
     for (size_t r = 0; r < count; ++r) {
         const auto& I = p->items[p->order[r]];
+        // tile numbers restart at 0 for each group's persistent launch
+        for (const auto& gr : p->groups)
+            if ((int)r == gr.first) tt = 0;
         const void* y = (const char*)y_base + I.it.in_offset * isz;
         pj[r] = make_prep_job(p, I.g, I.s, y, I.it.ld_in, nullptr, ws, I.table_off);
         cs[r] = cb;
@@ -722,6 +743,7 @@ corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
     ta.start = (const int32_t*)(dev + L.tstart);
     ta.count = (int32_t)nd;
     ta.counter = counter;
+    ta.ncounters = (int32_t)p->groups.size();
     e = launch_tables(ta, ((const int32_t*)(h + L.tstart))[nd], *std::max_element(p->distinct_m.begin(), p->distinct_m.end()), s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
@@ -739,13 +761,18 @@ corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
     hipGetDevice(&dev_id);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess || cus <= 0)
         cus = 256;
-    const int per_cu = persistent_blocks_per_cu(p->d.prec, p->tile.fm, p->tile.fn);
-    int64_t blocks = (int64_t)cus * per_cu;
-    blocks = std::min<int64_t>(blocks, p->total_tiles);
-    e = launch_corr_persistent(p->d.prec, p->tile.fm, p->tile.fn, (const CorrJob*)(dev + L.corr),
-                               (const int64_t*)(dev + L.tilestart), (int)count, p->total_tiles,
-                               counter, (int)blocks, s);
-    if (e != hipSuccess) return device_fail(e, "persistent correlation launch");
+    // one persistent launch per tile shape, each with its own ticket counter
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const auto& gr = p->groups[gi];
+        const int per_cu = persistent_blocks_per_cu(p->d.prec, gr.tile.fm, gr.tile.fn);
+        int64_t blocks = (int64_t)cus * per_cu;
+        blocks = std::min<int64_t>(blocks, gr.tiles);
+        e = launch_corr_persistent(p->d.prec, gr.tile.fm, gr.tile.fn,
+                                   (const CorrJob*)(dev + L.corr) + gr.first,
+                                   (const int64_t*)(dev + L.tilestart) + gr.first, gr.count, gr.tiles,
+                                   counter + gi, (int)blocks, s);
+        if (e != hipSuccess) return device_fail(e, "persistent correlation launch");
+    }
     return CORR2D_OK;
 }
 

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void tables_kernel(Src src) {
     double* tc = tw_lds;
     double* ts = tw_lds + T.m;
     double* hh = tw_lds + 2 * T.m;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && src.counter) *src.counter = 0;
+    if (blockIdx.x == 0 && src.counter && (int)threadIdx.x < src.ncounters) src.counter[threadIdx.x] = 0;
     for (int64_t i = threadIdx.x; i < T.m; i += blockDim.x) {
         double sv, cv;
         sincospi(2.0 * (double)i / (double)T.m, &sv, &cv);

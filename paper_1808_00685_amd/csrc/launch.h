@@ -14,7 +14,8 @@ struct TableSrcInline {
     TableJob j[2];
     int32_t blocks0;
     int32_t count;
-    int* counter;  // unused (nullptr); the batched source resets its ticket counter
+    int* counter;       // unused (nullptr); the batched source resets its ticket counters
+    int32_t ncounters;  // 0
     __device__ TableJob get(int b, int& lb) const {
         if (count == 1 || b < blocks0) { lb = b; return j[0]; }
         lb = b - blocks0;
@@ -28,8 +29,8 @@ struct TableSrcArray {
     const TableJob* jobs;
     const int32_t* start;
     int32_t count;
-    int32_t pad;
-    int* counter;  // set to 0 by block 0 (ticket counter of the persistent launch)
+    int32_t ncounters;  // ticket counters of the persistent launches (one per tile shape)
+    int* counter;       // set to 0 by block 0
     __device__ TableJob get(int b, int& lb) const {
         int lo = 0, hi = count - 1;
         while (lo < hi) {
