@@ -764,10 +764,11 @@ corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
     // one persistent launch per tile shape, each with its own ticket counter
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         const auto& gr = p->groups[gi];
-        const int per_cu = persistent_blocks_per_cu(p->d.prec, gr.tile.fm, gr.tile.fn);
+        const bool out_f64 = p->d.out_dtype == CORR2D_DTYPE_F64;
+        const int per_cu = persistent_blocks_per_cu(p->d.prec, gr.tile.fm, gr.tile.fn, out_f64);
         int64_t blocks = (int64_t)cus * per_cu;
         blocks = std::min<int64_t>(blocks, gr.tiles);
-        e = launch_corr_persistent(p->d.prec, gr.tile.fm, gr.tile.fn,
+        e = launch_corr_persistent(p->d.prec, gr.tile.fm, gr.tile.fn, out_f64,
                                    (const CorrJob*)(dev + L.corr) + gr.first,
                                    (const int64_t*)(dev + L.tilestart) + gr.first, gr.count, gr.tiles,
                                    counter + gi, (int)blocks, s);

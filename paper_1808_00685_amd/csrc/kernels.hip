@@ -24,6 +24,7 @@
 // of lane l holds column (l & 15) and row 4*(l >> 4) + q for the FP32-output
 // instructions, but row (l >> 4) + 4*q for v_mfma_f64_16x16x4f64 (measured).
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <math.h>
 #include <stdint.h>
 
@@ -675,8 +676,167 @@ __device__ inline void emit(const CorrJob& C, int64_t i, int64_t j, double phi, 
 }
 
 // One output tile (I, J) of size (32 FM) x (32 FN) computed by 4 waves (2x2).
+__device__ inline void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+// Barrier after this wave's own LDS writes (ds_write is asynchronous): wait
+// for them (lgkmcnt), but not for outstanding global stores (vmcnt).
+__device__ inline void lds_write_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue through LDS, shared by both contraction kernels
+// ---------------------------------------------------------------------------
+// An output tile of TM x TN values of type OT sits in LDS with a row pitch
+// of TN + 4 elements, already scaled by c / sR_j; store_tile writes it out
+// with NT threads as contiguous row runs (16-byte stores where the
+// destination allows): direct rows for heterocorrelation and the upper part
+// of a homocorrelation, the mirror of a FULL homocorrelation read transposed
+// from the same tile (Psi negated), or the rows of UPPER_PACKED.  The row
+// scale 1 / sL_i, a power of two, is applied exactly with ldexp as the rows
+// leave LDS; this equals one FP64 product unless the result is subnormal.
+
+// Exponent of a power-of-two scale.
+__device__ inline int pow2_exp(float s) { return ((__float_as_int(s) >> 23) & 0xff) - 127; }
+
+template <class OT> struct V4 { OT x, y, z, w; };
+template <class OT>
+__device__ inline V4<OT> row_unscale(V4<OT> v, int e) {
+    return V4<OT>{ldexp(v.x, e), ldexp(v.y, e), ldexp(v.z, e), ldexp(v.w, e)};
+}
+template <>
+__device__ inline V4<float> row_unscale(V4<float> v, int e) {
+    return V4<float>{ldexpf(v.x, e), ldexpf(v.y, e), ldexpf(v.z, e), ldexpf(v.w, e)};
+}
+
+template <class OT>
+__device__ inline void put4(void* base, int64_t idx, V4<OT> v, bool f64, bool aligned) {
+    if (f64) {
+        double* d = (double*)base + idx;
+        if (aligned) {
+            *(double2*)d = make_double2(v.x, v.y);
+            *(double2*)(d + 2) = make_double2(v.z, v.w);
+        } else {
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+    } else {
+        float* f = (float*)base + idx;
+        if (aligned) *(float4*)f = make_float4(v.x, v.y, v.z, v.w);
+        else { f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w; }
+    }
+}
+template <class OT>
+__device__ inline void put1(void* base, int64_t idx, OT v, bool f64) {
+    if (f64) ((double*)base)[idx] = v;
+    else ((float*)base)[idx] = (float)v;
+}
+
+template <int TM, int TN, int NT, class OT>
+__device__ inline void store_tile(const CorrJob& C, int64_t i0, int64_t j0, const OT* T, bool psi, int tid) {
+    constexpr int P = TN + 4;             // row pitch in elements
+    constexpr int RPP = NT / (TN / 4);    // rows per pass of the direct stores
+    static_assert(TM % RPP == 0, "direct-store passes");
+    const bool homo = C.homo;
+    const bool diag = homo && j0 <= i0 + TM - 1;   // tile reaches the diagonal
+    void* out = psi ? C.psi : C.phi;
+    const bool f64 = C.out_f64;
+    const bool inside = i0 + TM <= C.n1 && j0 + TN <= C.n2;
+    const int cl = (tid % (TN / 4)) * 4;  // 4 consecutive columns per thread
+    const int rsub = tid / (TN / 4);
+    if (!homo || C.layout == L_FULL) {
+        // direct rows (homo: the upper part; diagonal tiles mask j < i)
+        for (int pass = 0; pass < TM / RPP; ++pass) {
+            const int rl = pass * RPP + rsub;
+            const int64_t i = i0 + rl, j = j0 + cl;
+            V4<OT> v = *(const V4<OT>*)(T + rl * P + cl);
+            if (C.scaled && i < C.n1) v = row_unscale(v, -pow2_exp(C.sL[i]));
+            const int64_t idx = i * C.ld_out + j;
+            if (inside && !diag) {
+                put4(out, idx, v, f64, ((idx & 3) == 0) && ((C.ld_out & 3) == 0));
+            } else if (i < C.n1) {
+                const OT e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t jj = j + q;
+                    if (jj >= C.n2) break;
+                    if (diag && jj < i) continue;
+                    put1(out, idx + q, e[q], f64);
+                }
+            }
+        }
+        if (homo) {
+            // mirror: row jm = j0 + rr, columns i0 + cc..cc+3 take -(+)T[cc+q][rr]
+            // for Psi (Phi); diagonal tiles write only the strictly lower part
+            constexpr int MPP = NT / (TM / 4);   // mirror rows per pass
+            static_assert(TN % MPP == 0, "mirror passes");
+            const int cc = (tid % (TM / 4)) * 4;
+            const int rsubm = tid / (TM / 4);
+            const OT sg = psi ? OT(-1) : OT(1);
+            // rows i0 + cc .. cc+3 of the tile are this thread's mirror columns
+            int er[4] = {0, 0, 0, 0};
+            if (C.scaled)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (i0 + cc + q < C.n1) er[q] = -pow2_exp(C.sL[i0 + cc + q]);
+            for (int pass = 0; pass < TN / MPP; ++pass) {
+                const int rr = pass * MPP + rsubm;
+                const int64_t jm = j0 + rr, im = i0 + cc;
+                V4<OT> t{sg * T[(cc + 0) * P + rr], sg * T[(cc + 1) * P + rr],
+                         sg * T[(cc + 2) * P + rr], sg * T[(cc + 3) * P + rr]};
+                if (C.scaled)
+                    t = V4<OT>{ldexp(t.x, er[0]), ldexp(t.y, er[1]), ldexp(t.z, er[2]), ldexp(t.w, er[3])};
+                const int64_t midx = jm * C.ld_out + im;
+                if (inside && !diag) {
+                    put4(out, midx, t, f64, ((midx & 3) == 0) && ((C.ld_out & 3) == 0));
+                } else if (jm < C.n1) {
+                    const OT e[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t ii = im + q;
+                        if (ii >= C.n1) break;
+                        if (diag && ii >= jm) continue;   // strictly lower part (row jm > col ii)
+                        put1(out, midx + q, e[q], f64);
+                    }
+                }
+            }
+        }
+    } else {
+        // UPPER_PACKED: element (i, j) at rowbase(i) + j, j >= i
+        for (int pass = 0; pass < TM / RPP; ++pass) {
+            const int rl = pass * RPP + rsub;
+            const int64_t i = i0 + rl, j = j0 + cl;
+            if (i >= C.n1) break;
+            V4<OT> v = *(const V4<OT>*)(T + rl * P + cl);
+            if (C.scaled) v = row_unscale(v, -pow2_exp(C.sL[i]));
+            const int64_t idx = packed_row_base(i, C.n1) + j;
+            if (inside && !diag) {
+                put4(out, idx, v, f64, (idx & 3) == 0);
+            } else {
+                const OT e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t jj = j + q;
+                    if (jj >= C.n2) break;
+                    if (jj < i) continue;
+                    put1(out, idx + q, e[q], f64);
+                }
+            }
+        }
+    }
+}
+
+// Dynamic LDS of the register-direct kernel: one output plane of its tile.
+__host__ __device__ constexpr int corr_lds_bytes(int fm, int fn, bool out_f64) {
+    return 32 * fm * (32 * fn + 4) * (out_f64 ? 8 : 4);
+}
+
 template <int P, int FM, int FN>
-__device__ inline void corr_tile(const CorrJob& C, int I, int J) {
+__device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds) {
     using FT = typename Frag<P>::T;
     using AT = typename Frag<P>::Acc;
     constexpr int KS = Frag<P>::KS;
@@ -729,19 +889,38 @@ __device__ inline void corr_tile(const CorrJob& C, int I, int J) {
             }
     }
 
+    // epilogue through LDS in the output type, Phi then Psi
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int64_t ti0 = (int64_t)I * BM, tj0 = (int64_t)J * BN;
+    const bool diag = C.homo && tj0 <= ti0 + BM - 1;
+    auto stage = [&](auto* T, AT (&acc)[FM][FN], bool psi) {
+        using OT = typename std::remove_pointer<decltype(T)>::type;
+        lds_barrier();   // previous readers of the LDS are done
 #pragma unroll
-    for (int b = 0; b < FN; ++b) {
-        const int64_t j = j0 + b * 16 + row16;
-        double fa, fb;
-        col_factors(C, j, fa, fb);
+        for (int b = 0; b < FN; ++b) {
+            const int jl = (int)(j0 - tj0) + b * 16 + row16;
+            double fc = C.c;
+            if (C.scaled) fc *= inv_pow2(psi ? C.sRB[tj0 + jl] : C.sRA[tj0 + jl]);
 #pragma unroll
-        for (int a = 0; a < FM; ++a)
+            for (int a = 0; a < FM; ++a)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t i = i0 + a * 16 + (P == P_F64 ? kg + 4 * q : kg * 4 + q);
-                const double rf = row_factor(C, i);
-                emit(C, i, j, (double)ap[a][b][q] * fa * rf, (double)aq[a][b][q] * fb * rf);
-            }
+                for (int q = 0; q < 4; ++q) {
+                    const int il = (int)(i0 - ti0) + a * 16 + (P == P_F64 ? kg + 4 * q : kg * 4 + q);
+                    OT v = (OT)((double)acc[a][b][q] * fc);
+                    if (psi && diag && ti0 + il == tj0 + jl) v = OT(0);
+                    T[il * (BN + 4) + jl] = v;
+                }
+        }
+        lds_write_barrier();
+        store_tile<BM, BN, 256, OT>(C, ti0, tj0, T, psi, tid);
+    };
+    if (C.out_f64) {
+        stage((double*)lds, ap, false);
+        stage((double*)lds, aq, true);
+    } else {
+        stage((float*)lds, ap, false);
+        stage((float*)lds, aq, true);
     }
 }
 
@@ -790,12 +969,11 @@ template <int P, int TM> constexpr int stage_bytes() { return planes(P) * (TM * 
 template <int P, int TM> constexpr int ring_stages() {
     return TM == 256 ? (planes(P) == 2 ? 4 : 8) : (planes(P) == 2 ? 3 : 6);
 }
-constexpr int kOutPitch = 132;   // floats per row of the LDS output tile (128 + 4)
 // LDS of a contraction workgroup: the operand ring, reused by the output tile
 template <int P, int TM> constexpr int corr2_lds_bytes() {
-    return ring_stages<P, TM>() * stage_bytes<P, TM>() > TM * kOutPitch * 4
+    return ring_stages<P, TM>() * stage_bytes<P, TM>() > TM * (kTileN2 + 4) * 4
                ? ring_stages<P, TM>() * stage_bytes<P, TM>()
-               : TM * kOutPitch * 4;
+               : TM * (kTileN2 + 4) * 4;
 }
 
 template <int N>
@@ -813,60 +991,14 @@ __device__ inline void wait_stages(int ahead) {
         else wait_stages<OPSW, MAXA - 1>(ahead);
     }
 }
-__device__ inline void lds_barrier() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-// Barrier after this wave's own LDS writes (ds_write is asynchronous): wait
-// for them (lgkmcnt), but not for outstanding global stores (vmcnt).
-__device__ inline void lds_write_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
-// Epilogue of one TM x 128 output tile of Phi (psi = false) or Psi.
-// The waves normalize their accumulators in FP64 by the column factor
-// c / sR_j, round once to FP32 and write them into an LDS tile (the operand
-// ring is free by then); all threads then store rows of the tile as
-// contiguous runs: 16-byte stores where the destination allows, the mirror
-// of a FULL homocorrelation read transposed from the same tile.  The row
-// scale 1 / sL_i (a power of two) is applied exactly with ldexp as the
-// rows leave LDS; this equals the single FP64 product unless the result is
-// an FP32 subnormal.  Accumulator register r of lane l holds row
+// Epilogue of one TM x 128 output tile of the LDS-staged kernel.  The waves
+// scale their accumulators in FP64 by the column factor, round once to FP32
+// and write them into an LDS tile (the operand ring is free by then), then
+// store_tile writes it out.  Accumulator register r of lane l holds row
 // 8(r/4) + 4(l/32) + r%4 and column l%32 of its 32 x 32 block.
-
-// Exponent of a power-of-two scale.
-__device__ inline int pow2_exp(float s) { return ((__float_as_int(s) >> 23) & 0xff) - 127; }
-__device__ inline float4 row_unscale(float4 v, float s) {
-    const int e = -pow2_exp(s);
-    return make_float4(ldexpf(v.x, e), ldexpf(v.y, e), ldexpf(v.z, e), ldexpf(v.w, e));
-}
-
-__device__ inline void put4(void* base, int64_t idx, float4 v, bool f64, bool aligned) {
-    if (f64) {
-        double* d = (double*)base + idx;
-        if (aligned) {
-            *(double2*)d = make_double2(v.x, v.y);
-            *(double2*)(d + 2) = make_double2(v.z, v.w);
-        } else {
-            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-        }
-    } else {
-        float* f = (float*)base + idx;
-        if (aligned) *(float4*)f = v;
-        else { f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w; }
-    }
-}
-__device__ inline void put1(void* base, int64_t idx, float v, bool f64) {
-    if (f64) ((double*)base)[idx] = v;
-    else ((float*)base)[idx] = v;
-}
-
 template <int TM>
 __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][2], char* lds, bool psi) {
-    constexpr int NT = threads2(TM);
     float* T = (float*)lds;
     // opaque copy of the thread index: keeps the index arithmetic below
     // inside a persistent tile loop instead of hoisted and spilled
@@ -874,10 +1006,8 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, w = tid >> 6;
     const int wi = w >> 1, wj = w & 1, g = lane >> 5;
-    const bool homo = C.homo;
     const int64_t i0 = (int64_t)I * TM, j0 = (int64_t)J * kTileN2;
-    // homocorrelation tiles that reach down to the diagonal (j <= i somewhere)
-    const bool diag = homo && j0 <= i0 + TM - 1;
+    const bool diag = C.homo && j0 <= i0 + TM - 1;
     lds_barrier();   // previous readers of the LDS are done
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
@@ -891,94 +1021,11 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
                 const int il = wi * 64 + a * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
                 float v = (float)((double)acc[a][b][r] * fc);
                 if (psi && diag && i0 + il == j0 + jl) v = 0.0f;
-                T[il * kOutPitch + jl] = v;
+                T[il * (kTileN2 + 4) + jl] = v;
             }
     }
     lds_write_barrier();
-    void* out = psi ? C.psi : C.phi;
-    const bool f64 = C.out_f64;
-    const bool inside = i0 + TM <= C.n1 && j0 + kTileN2 <= C.n2;
-    if (!homo || C.layout == L_FULL) {
-        // direct rows (homo: the upper part; diagonal tiles mask j < i)
-        const int cl = (tid & 31) * 4;   // 4 consecutive columns per thread
-        const int rsub = tid >> 5;        // NT / 32 rows per pass
-        for (int pass = 0; pass < TM / (NT / 32); ++pass) {
-            const int rl = pass * (NT / 32) + rsub;
-            const int64_t i = i0 + rl, j = j0 + cl;
-            float4 v = *(const float4*)(T + rl * kOutPitch + cl);
-            if (C.scaled) v = row_unscale(v, C.sL[i]);
-            const int64_t idx = i * C.ld_out + j;
-            if (inside && !diag) {
-                put4(out, idx, v, f64, ((idx & 3) == 0) && ((C.ld_out & 3) == 0));
-            } else if (i < C.n1) {
-                const float e[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t jj = j + q;
-                    if (jj >= C.n2) break;
-                    if (diag && jj < i) continue;
-                    put1(out, idx + q, e[q], f64);
-                }
-            }
-        }
-        if (homo) {
-            // mirror: row jm = j0 + rr, columns i0 + cc..cc+3 take -(+)T[cc+q][rr]
-            // for Psi (Phi); diagonal tiles write only the strictly lower part
-            const int cc = (tid % (TM / 4)) * 4;   // TM / 4 threads x 4 columns
-            const int rsub8 = tid / (TM / 4);      // 8 rows per pass
-            const float sg = psi ? -1.0f : 1.0f;
-            // rows i0 + cc .. cc+3 of the tile are this thread's mirror columns
-            int er[4] = {0, 0, 0, 0};
-            if (C.scaled)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) er[q] = -pow2_exp(C.sL[i0 + cc + q]);
-            for (int pass = 0; pass < kTileN2 / 8; ++pass) {
-                const int rr = pass * 8 + rsub8;
-                const int64_t jm = j0 + rr, im = i0 + cc;
-                const float4 t = make_float4(ldexpf(sg * T[(cc + 0) * kOutPitch + rr], er[0]),
-                                             ldexpf(sg * T[(cc + 1) * kOutPitch + rr], er[1]),
-                                             ldexpf(sg * T[(cc + 2) * kOutPitch + rr], er[2]),
-                                             ldexpf(sg * T[(cc + 3) * kOutPitch + rr], er[3]));
-                const int64_t midx = jm * C.ld_out + im;
-                if (inside && !diag) {
-                    put4(out, midx, t, f64, ((midx & 3) == 0) && ((C.ld_out & 3) == 0));
-                } else if (jm < C.n1) {
-                    const float e[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int64_t ii = im + q;
-                        if (ii >= C.n1) break;
-                        if (diag && ii >= jm) continue;   // strictly lower part (row jm > col ii)
-                        put1(out, midx + q, e[q], f64);
-                    }
-                }
-            }
-        }
-    } else {
-        // UPPER_PACKED: element (i, j) at rowbase(i) + j, j >= i
-        const int cl = (tid & 31) * 4;
-        const int rsub = tid >> 5;
-        for (int pass = 0; pass < TM / (NT / 32); ++pass) {
-            const int rl = pass * (NT / 32) + rsub;
-            const int64_t i = i0 + rl, j = j0 + cl;
-            if (i >= C.n1) break;
-            float4 v = *(const float4*)(T + rl * kOutPitch + cl);
-            if (C.scaled) v = row_unscale(v, C.sL[i]);
-            const int64_t idx = packed_row_base(i, C.n1) + j;
-            if (inside && !diag) {
-                put4(out, idx, v, f64, (idx & 3) == 0);
-            } else {
-                const float e[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t jj = j + q;
-                    if (jj >= C.n2) break;
-                    if (jj < i) continue;
-                    put1(out, idx + q, e[q], f64);
-                }
-            }
-        }
-    }
+    store_tile<TM, kTileN2, threads2(TM), float>(C, i0, j0, T, psi, tid);
 }
 
 // One TM x 128 output tile: the K loop over a ring of LDS stages filled by
@@ -1164,11 +1211,12 @@ __global__ __launch_bounds__(threads2(TM), 512 / TM) void corr2_persistent_kerne
 
 template <int P, int FM, int FN>
 __global__ __launch_bounds__(256) void corr_kernel(CorrJob C) {
+    extern __shared__ __attribute__((aligned(16))) char corr_lds[];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
     if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
     else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
-    corr_tile<P, FM, FN>(C, I, J);
+    corr_tile<P, FM, FN>(C, I, J, corr_lds);
 }
 
 // Persistent batched contraction: workgroups take tiles from a global ticket
@@ -1178,11 +1226,12 @@ __global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* job
                                                                const int64_t* tile_start,
                                                                int count, int64_t total,
                                                                int* counter) {
+    extern __shared__ __attribute__((aligned(16))) char corr_lds[];
     __shared__ int64_t s_t;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
         __syncthreads();
-        const int64_t t = s_t;
+        const int64_t t = uniform64(s_t);
         __syncthreads();
         if (t >= total) break;
         int lo = 0, hi = count - 1;
@@ -1194,7 +1243,7 @@ __global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* job
         const CorrJob C = jobs[lo];
         int I, J;
         decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
-        corr_tile<P, FM, FN>(C, I, J);
+        corr_tile<P, FM, FN>(C, I, J, corr_lds);
     }
 }
 
@@ -1252,7 +1301,8 @@ hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t block
 #undef Y
 #define X(PP, A, B)                                                                          \
     if (prec == PP && fm == A && fn == B) {                                                  \
-        hipLaunchKernelGGL((corr_kernel<PP, A, B>), dim3((unsigned)blocks), dim3(256), 0, s, C); \
+        hipLaunchKernelGGL((corr_kernel<PP, A, B>), dim3((unsigned)blocks), dim3(256),         \
+                           corr_lds_bytes(A, B, C.out_f64), s, C);                           \
         return hipGetLastError();                                                            \
     }
     CORR_CASES(X)
@@ -1260,7 +1310,7 @@ hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t block
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
+hipError_t launch_corr_persistent(int prec, int fm, int fn, bool out_f64, const CorrJob* jobs,
                                   const int64_t* tile_start, int count, int64_t total,
                                   int* counter, int blocks, hipStream_t s) {
 #define Y(PP)                                                                                 \
@@ -1277,8 +1327,8 @@ hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
 #undef Y
 #define X(PP, A, B)                                                                         \
     if (prec == PP && fm == A && fn == B) {                                                 \
-        hipLaunchKernelGGL((corr_persistent_kernel<PP, A, B>), dim3(blocks), dim3(256), 0, s, jobs, \
-                           tile_start, count, total, counter);                              \
+        hipLaunchKernelGGL((corr_persistent_kernel<PP, A, B>), dim3(blocks), dim3(256),        \
+                           corr_lds_bytes(A, B, out_f64), s, jobs, tile_start, count, total, counter); \
         return hipGetLastError();                                                           \
     }
     CORR_CASES(X)
@@ -1296,7 +1346,7 @@ int corr_variant_supported(int prec, int fm, int fn) {
     return 0;
 }
 
-int persistent_blocks_per_cu(int prec, int fm, int fn) {
+int persistent_blocks_per_cu(int prec, int fm, int fn, bool out_f64) {
     int n = 0;
 #define Y(PP)                                                                             \
     if (prec == PP && (fm == 8 || fm == 4) && fn == 4) {                                  \
@@ -1310,8 +1360,9 @@ int persistent_blocks_per_cu(int prec, int fm, int fn) {
 #undef Y
 #define X(PP, A, B)                                                                      \
     if (prec == PP && fm == A && fn == B) {                                              \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr_persistent_kernel<PP, A, B>, 256, 0) \
-            != hipSuccess) n = 1;                                                        \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, corr_persistent_kernel<PP, A, B>, 256, \
+                                                         corr_lds_bytes(A, B, out_f64)) != hipSuccess) \
+            n = 1;                                                                       \
         return n > 0 ? n : 1;                                                            \
     }
     CORR_CASES(X)

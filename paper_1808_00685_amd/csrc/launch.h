@@ -79,10 +79,10 @@ hipError_t launch_center(const PrepSrcArray& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s);
 hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s);
-hipError_t launch_corr_persistent(int prec, int fm, int fn, const CorrJob* jobs,
+hipError_t launch_corr_persistent(int prec, int fm, int fn, bool out_f64, const CorrJob* jobs,
                                   const int64_t* tile_start, int count, int64_t total,
                                   int* counter, int blocks, hipStream_t s);
 int corr_variant_supported(int prec, int fm, int fn);
-int persistent_blocks_per_cu(int prec, int fm, int fn);
+int persistent_blocks_per_cu(int prec, int fm, int fn, bool out_f64);
 
 }  // namespace corr2d
