@@ -20,6 +20,9 @@ marshals numpy arrays and combines the paper's normalization readings:
   the paper's default ``Norm``; "custom" cF = ``norm_value``.  Since the
   weighted Fourier sum of real data is m times the time-domain sum (Parseval),
   the direct route under norm cF is the "noda" result times cF*m*(m-1).
+* Scaling ``alpha`` (Sec. 2 Eqs. (stdev), (scalesyn), (scaleasyn)): the result
+  divided by (sigma_1 sigma_2)^alpha, sigma per spectral variable from the
+  dynamic spectra in use; a variable with sigma = 0 is left unscaled.
 
 Parity pins (tests/test_oracle_pins.py) tie every function here to closed
 forms, invariants and an independent padded-Fourier algorithm.
@@ -220,8 +223,31 @@ def norm_factor(m, norm="noda", norm_value=None):
     raise ValueError(norm)
 
 
-def corr2d(S1, S2=None, ref1=None, ref2=None, hilbert="noda", norm="noda", norm_value=None):
-    """Full (phi, psi) for homocorrelation (S2 None) or heterocorrelation."""
+def band_sd(Y):
+    """sigma_nu of every spectral variable (column) of the dynamic spectra Y,
+    Sec. 2 Eq. (stdev): sqrt(sum_j Y[j, nu]^2 / (m - 1)), Y already centred on
+    the reference in use."""
+    Y = np.asarray(Y, dtype=np.float64)
+    return np.sqrt(np.sum(Y * Y, axis=0) / (Y.shape[0] - 1))
+
+
+def scaling_factors(sd, alpha):
+    """sigma^-alpha per spectral variable; 1 where sigma = 0 (that variable's
+    dynamic spectrum is zero, so leaving it unscaled changes nothing)."""
+    sd = np.asarray(sd, dtype=np.float64)
+    f = np.ones_like(sd)
+    nz = sd > 0
+    f[nz] = sd[nz] ** (-float(alpha))
+    return f
+
+
+def corr2d(S1, S2=None, ref1=None, ref2=None, hilbert="noda", norm="noda", norm_value=None,
+           alpha=0.0):
+    """Full (phi, psi) for homocorrelation (S2 None) or heterocorrelation.
+
+    alpha != 0 applies the scaling of Sec. 2 Eqs. (scalesyn), (scaleasyn), read
+    as phi / (sigma_1 sigma_2)^alpha (Pearson alpha = 1, Pareto 0.5) with the
+    sigma of Eq. (stdev) per spectral variable of each set."""
     Y1, _ = dynamic(S1, ref1)
     Y2 = Y1 if S2 is None else dynamic(S2, ref2)[0]
     m = Y1.shape[0]
@@ -232,14 +258,19 @@ def corr2d(S1, S2=None, ref1=None, ref2=None, hilbert="noda", norm="noda", norm_
         if f != 1.0:
             phi = phi * f
             psi = psi * f
-        return phi, psi
-    if hilbert == "circular":
-        return corr_ft_circular(Y1, Y2, cF)
-    raise ValueError(hilbert)
+    elif hilbert == "circular":
+        phi, psi = corr_ft_circular(Y1, Y2, cF)
+    else:
+        raise ValueError(hilbert)
+    if alpha != 0.0:
+        w = np.outer(scaling_factors(band_sd(Y1), alpha), scaling_factors(band_sd(Y2), alpha))
+        phi = phi * w
+        psi = psi * w
+    return phi, psi
 
 
 def corr2d_entries(S1, rows, cols, S2=None, ref1=None, ref2=None, hilbert="noda",
-                   norm="noda", norm_value=None):
+                   norm="noda", norm_value=None, alpha=0.0):
     """Selected entries of corr2d(); the dynamic spectra are formed in full."""
     Y1, _ = dynamic(S1, ref1)
     Y2 = Y1 if S2 is None else dynamic(S2, ref2)[0]
@@ -251,7 +282,14 @@ def corr2d_entries(S1, rows, cols, S2=None, ref1=None, ref2=None, hilbert="noda"
         if f != 1.0:
             phi = phi * f
             psi = psi * f
-        return phi, psi
-    if hilbert == "circular":
-        return corr_ft_circular_entries(Y1, Y2, cF, rows, cols)
-    raise ValueError(hilbert)
+    elif hilbert == "circular":
+        phi, psi = corr_ft_circular_entries(Y1, Y2, cF, rows, cols)
+    else:
+        raise ValueError(hilbert)
+    if alpha != 0.0:
+        rows, cols = np.asarray(rows), np.asarray(cols)
+        w = (scaling_factors(band_sd(Y1), alpha)[rows] *
+             scaling_factors(band_sd(Y2), alpha)[cols])
+        phi = phi * w
+        psi = psi * w
+    return phi, psi

@@ -335,3 +335,75 @@ def test_workload_generators_are_seeded_and_shaped():
     assert Sa.shape == (16, 64) and Sb.shape == (16, 32)
     items = synth.batch_spec(count=8)
     assert all(8 <= it.m <= 200 and 256 <= it.n <= 8192 for it in items)
+
+
+# --------------------------------------------------------------------------
+# Scaling (Sec. 2 Eqs. (stdev), (pearsonsyn), (scalesyn), (scaleasyn))
+# --------------------------------------------------------------------------
+def _scaling_data(m=13, n=40, seed=5):
+    rng = np.random.default_rng(seed)
+    S = rng.standard_normal((m, n)) * rng.uniform(0.01, 100.0, size=n) + rng.uniform(-5, 5, size=n)
+    return S
+
+
+def test_band_sd_is_sample_std():
+    S = _scaling_data()
+    Y, _ = oracle.dynamic(S)
+    assert np.allclose(oracle.band_sd(Y), np.std(S, axis=0, ddof=1), rtol=1e-13, atol=0)
+
+
+def test_pearson_synchronous_is_correlation_coefficient_matrix():
+    # Pearson scaling of the synchronous spectrum with the mean reference is
+    # the matrix of correlation coefficients between spectral variables
+    S = _scaling_data()
+    phi, psi = oracle.corr2d(S, alpha=1.0)
+    R = np.corrcoef(S, rowvar=False)
+    assert np.allclose(phi, R, rtol=0, atol=1e-13)
+    assert np.allclose(np.diag(phi), 1.0, atol=1e-14)
+    assert np.abs(phi).max() <= 1.0 + 1e-13
+    assert np.allclose(psi, -psi.T, atol=1e-15)
+
+
+def test_pearson_hetero_is_cross_correlation_block():
+    S1, S2 = _scaling_data(seed=6), _scaling_data(n=25, seed=7)
+    phi, _ = oracle.corr2d(S1, S2, alpha=1.0)
+    R = np.corrcoef(np.hstack([S1, S2]), rowvar=False)[:S1.shape[1], S1.shape[1]:]
+    assert np.allclose(phi, R, rtol=0, atol=1e-13)
+
+
+def test_pareto_relation_to_pearson():
+    # (Phi / (s1 s2)^0.5)^2 = Phi * Phi / (s1 s2), elementwise, for both spectra
+    S = _scaling_data()
+    p0, q0 = oracle.corr2d(S)
+    ph, qh = oracle.corr2d(S, alpha=0.5)
+    p1, q1 = oracle.corr2d(S, alpha=1.0)
+    assert np.allclose(ph * ph, p0 * p1, rtol=1e-12, atol=1e-300)
+    assert np.allclose(qh * qh, q0 * q1, rtol=1e-12, atol=1e-300)
+
+
+def test_pearson_invariant_to_band_rescaling():
+    S = _scaling_data()
+    d = np.random.default_rng(3).uniform(0.001, 1000.0, size=S.shape[1])
+    p1, q1 = oracle.corr2d(S, alpha=1.0)
+    p2, q2 = oracle.corr2d(S * d, alpha=1.0)
+    assert np.allclose(p1, p2, rtol=1e-11, atol=1e-13)
+    assert np.allclose(q1, q2, rtol=1e-11, atol=1e-13)
+
+
+def test_scaling_general_alpha_and_zero_variance():
+    S = _scaling_data()
+    S[:, 4] = 3.25            # constant band: sigma = 0, left unscaled
+    Y, _ = oracle.dynamic(S)
+    sd = np.std(S, axis=0, ddof=1)
+    p0, q0 = oracle.corr2d(S)
+    a = 0.3
+    p, q = oracle.corr2d(S, alpha=a)
+    w = np.where(sd > 0, sd, 1.0) ** (-a)
+    assert np.allclose(p, p0 * np.outer(w, w), rtol=1e-13, atol=0)
+    assert np.allclose(q, q0 * np.outer(w, w), rtol=1e-13, atol=0)
+    assert np.all(np.isfinite(p)) and np.all(p[4] == 0) and np.all(q[:, 4] == 0)
+    # entries agree with the full result, with the circular kernel too
+    i = np.array([0, 3, 7, 39]); j = np.array([5, 3, 21, 0])
+    pe, qe = oracle.corr2d_entries(S, i, j, alpha=a, hilbert="circular", norm="paper")
+    pf, qf = oracle.corr2d(S, alpha=a, hilbert="circular", norm="paper")
+    assert np.allclose(pe, pf[i, j], rtol=1e-13) and np.allclose(qe, qf[i, j], rtol=1e-13)
