@@ -115,6 +115,12 @@ typedef struct corr2d_desc {
                            256 x 128 (split-BF16, BF16, FP16); 3 = 128 x 128
                            (split-BF16, BF16, FP16)                             */
     int32_t reserved;
+    double scale_alpha; /* exponent alpha of the result scaling: Phi and Psi
+                           divided by (sigma_1 sigma_2)^alpha, Sec. 2 Eqs.
+                           (stdev), (scalesyn), (scaleasyn); 0 = unscaled,
+                           1 = Pearson, 0.5 = Pareto.  sigma per spectral
+                           variable from the dynamic spectrum in use; a
+                           variable with sigma = 0 stays unscaled.  Finite.     */
 } corr2d_desc;
 
 /* One data set of a batched homocorrelation.  Offsets are in elements from

@@ -43,6 +43,7 @@ class corr2d_desc(ctypes.Structure):
         ("basis", ctypes.c_int32), ("hilbert", ctypes.c_int32), ("norm_mode", ctypes.c_int32),
         ("norm_value", ctypes.c_double), ("out_layout", ctypes.c_int32),
         ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("scale_alpha", ctypes.c_double),
     ]
 
 
@@ -260,7 +261,7 @@ class Plan:
 
 
 def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="fourier",
-         hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, stream=None):
+         hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0, stream=None):
     """Homocorrelation of y (torch, m x n, float64/float32, on the GPU)."""
     import torch
     m, n = y.shape
@@ -269,7 +270,8 @@ def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="f
     plan = Plan(m=m, n1=n, n2=0, ld_in1=y.stride(0),
                 in_dtype="f64" if y.dtype == torch.float64 else "f32",
                 out_dtype=out_dtype, prec=prec, basis=basis, hilbert=hilbert, norm_mode=norm,
-                norm_value=norm_value, out_layout=layout, flags=flags, tile=tile)
+                norm_value=norm_value, out_layout=layout, flags=flags, tile=tile,
+                scale_alpha=alpha)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     numel = n * (n + 1) // 2 if layout == "upper_packed" else n * n
     phi = torch.empty(numel, dtype=tdt, device=y.device)
@@ -282,7 +284,7 @@ def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="f
 
 
 def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basis="fourier",
-           hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, stream=None):
+           hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0, stream=None):
     import torch
     m, n1 = y1.shape
     m2, n2 = y2.shape
@@ -292,7 +294,8 @@ def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basi
     plan = Plan(m=m, n1=n1, n2=n2, ld_in1=y1.stride(0), ld_in2=y2.stride(0),
                 in_dtype="f64" if y1.dtype == torch.float64 else "f32",
                 out_dtype=out_dtype, prec=prec, basis=basis, hilbert=hilbert, norm_mode=norm,
-                norm_value=norm_value, out_layout="full", flags=flags, tile=tile)
+                norm_value=norm_value, out_layout="full", flags=flags, tile=tile,
+                scale_alpha=alpha)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     phi = torch.empty(n1, n2, dtype=tdt, device=y1.device)
     psi = torch.empty(n1, n2, dtype=tdt, device=y1.device)

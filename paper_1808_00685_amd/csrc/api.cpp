@@ -167,6 +167,8 @@ corr2d_status check_common(const corr2d_desc* d) {
     if (!valid_enum(d->out_layout, 0, 1)) return fail(CORR2D_EINVAL, "unknown out_layout %d", d->out_layout);
     if (d->norm_mode == CORR2D_NORM_CUSTOM && !std::isfinite(d->norm_value))
         return fail(CORR2D_EINVAL, "CUSTOM norm needs a finite norm_value");
+    if (!std::isfinite(d->scale_alpha))
+        return fail(CORR2D_EINVAL, "scale_alpha must be finite");
     if (d->flags & ~0xfu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
     if (d->prec == CORR2D_PREC_FP8_E4M3 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
         return fail(CORR2D_EUNSUPPORTED, "FP8 e4m3 requires per-band scaling (range 448)");
@@ -282,6 +284,7 @@ PrepJob make_prep_job(const corr2d_plan_s* p, const Geo& g, const SetLayout& s, 
     j.A1 = s.A1 ? at<char>(ws, s.A1) : nullptr;
     j.B0 = s.has_b ? at<char>(ws, s.B0) : nullptr;
     j.B1 = (s.has_b && s.B1) ? at<char>(ws, s.B1) : nullptr;
+    j.alpha = p->d.scale_alpha;
     return j;
 }
 

@@ -80,6 +80,7 @@ struct PrepJob {
     float* sB;            // n_pad scales of operand B
     void* A0; void* A1;   // operand A planes, n_pad x kp (A1: split low plane)
     void* B0; void* B1;   // operand B planes
+    double alpha;         // result scaling exponent (0: none): columns x sigma^-alpha
 };
 
 // One correlation contraction (a homocorrelation or a heterocorrelation).

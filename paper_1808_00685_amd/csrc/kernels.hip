@@ -268,7 +268,11 @@ __device__ inline float pow2_scale(double qhalf, double bound) {
 // Workgroup: 32 spectral points x 8 row groups.  Pass 1 sums each column
 // (FP64); pass 2 subtracts the mean (FP64) and writes the centred column
 // transposed (its m values contiguous) through an LDS tile.  For m <= 256
-// (CACHE) the values read in pass 1 stay in registers for pass 2.
+// (CACHE) the values read in pass 1 stay in registers for pass 2.  With a
+// result scaling exponent alpha, a pass between them takes the column's
+// sigma = sqrt(sum (y - ref)^2 / (m - 1)) (two-pass, FP64) and the centred
+// column is multiplied by sigma^-alpha (1 for sigma = 0): the contraction is
+// bilinear, so Phi and Psi come out divided by (sigma_1 sigma_2)^alpha.
 template <class Src, bool CACHE>
 __device__ inline void center_body(const PrepJob& J, int lb) {
     constexpr int CW = kCenterCols, G = 256 / kCenterCols, MAXV = 32;
@@ -314,6 +318,32 @@ __device__ inline void center_body(const PrepJob& J, int lb) {
         __syncthreads();
     }
 
+    double gsc = 1.0;   // sigma^-alpha of this column
+    if (J.alpha != 0.0) {
+        double q0 = 0.0, q1 = 0.0;
+        if (CACHE) {
+#pragma unroll
+            for (int k = 0; k < MAXV; k += 2) {
+                const int64_t j = g + (int64_t)G * k;
+                if (valid && j < J.m) q0 += (vals[k] - mean) * (vals[k] - mean);
+                if (valid && j + G < J.m) q1 += (vals[k + 1] - mean) * (vals[k + 1] - mean);
+            }
+        } else if (valid) {
+            for (int64_t j = g; j < J.m; j += G) {
+                const double d = load_in(J, j, col) - mean;
+                q0 += d * d;
+            }
+        }
+        red[g][c] = q0 + q1;
+        __syncthreads();
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) t += red[q][c];
+        const double sd = sqrt(t / (double)(J.m - 1));
+        if (sd > 0.0) gsc = pow(sd, -J.alpha);
+        __syncthreads();
+    }
+
     double nrm = 0.0;
     const int cc = tid / G, part = tid % G;        // writer: column cc, 8 values
     const int64_t ocol = (int64_t)lb * CW + cc;
@@ -330,9 +360,9 @@ __device__ inline void center_body(const PrepJob& J, int lb) {
 #pragma unroll
                     for (int k = 0; k < MAXV; ++k)
                         if (k == j0 / G + q) x = vals[k];
-                    v = x - mean;
+                    v = (x - mean) * gsc;
                 } else {
-                    v = load_in(J, j, col) - mean;
+                    v = (load_in(J, j, col) - mean) * gsc;
                 }
             }
             nrm += v * v;

@@ -63,8 +63,9 @@ def test_struct_layout_matches_binding():
 #include <stddef.h>
 #include "corr2d.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu\n", sizeof(corr2d_desc), offsetof(corr2d_desc, norm_value),
-        offsetof(corr2d_desc, tile), sizeof(corr2d_item), sizeof(corr2d_plan_info));
+ printf("%zu %zu %zu %zu %zu %zu\n", sizeof(corr2d_desc), offsetof(corr2d_desc, norm_value),
+        offsetof(corr2d_desc, tile), offsetof(corr2d_desc, scale_alpha), sizeof(corr2d_item),
+        sizeof(corr2d_plan_info));
  return 0;}
 '''
     import tempfile
@@ -75,8 +76,8 @@ int main(void){
         subprocess.run(["gcc", "-I" + os.path.dirname(HEADER), c, "-o", exe], check=True)
         vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert vals == [ctypes.sizeof(B.corr2d_desc), B.corr2d_desc.norm_value.offset,
-                    B.corr2d_desc.tile.offset, ctypes.sizeof(B.corr2d_item),
-                    ctypes.sizeof(B.corr2d_plan_info)]
+                    B.corr2d_desc.tile.offset, B.corr2d_desc.scale_alpha.offset,
+                    ctypes.sizeof(B.corr2d_item), ctypes.sizeof(B.corr2d_plan_info)]
 
 
 def test_defaults():
@@ -119,6 +120,9 @@ def _plan_status(**kw):
     (dict(prec=0, tile=2), B.EUNSUPPORTED),
     (dict(prec=1, tile=3), B.EUNSUPPORTED),
     (dict(prec=2, tile=3), B.OK),
+    (dict(scale_alpha=float("nan")), B.EINVAL),
+    (dict(scale_alpha=float("inf")), B.EINVAL),
+    (dict(scale_alpha=0.5), B.OK),
     (dict(m=5000), B.EUNSUPPORTED),
     (dict(m=2, n1=1), B.OK),
     (dict(prec=5), B.OK),

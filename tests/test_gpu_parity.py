@@ -238,3 +238,60 @@ def test_medium_workload_full(gpu, prec):
     check_homo_structure(phi, psi)
     assert rel_fro(phi, phi_o) <= TOL[prec]
     assert rel_fro(psi, psi_o) <= TOL[prec]
+
+
+# --------------------------------------------------------------------------
+# Result scaling (Pearson, Pareto, general alpha)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"])
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_scaling_parity(gpu, prec, alpha):
+    m, n = 23, 300
+    rng = np.random.default_rng(91)
+    # bands of very different intensity: scaling evens them out
+    S = _rand(m, n, 90) * rng.uniform(1e-3, 1e2, size=n)
+    S[:, 7] = 2.0             # constant variable: sigma = 0, left unscaled
+    phi_o, psi_o = oracle.corr2d(S, alpha=alpha)
+    phi, psi, _ = _homo(S, gpu, prec=prec, alpha=alpha)
+    check_homo_structure(phi, psi)
+    assert rel_fro(phi, phi_o) <= TOL[prec]
+    assert rel_fro(psi, psi_o) <= TOL[prec]
+    assert np.all(phi[7] == 0) and np.all(psi[:, 7] == 0)
+    if alpha == 1.0 and prec in ("f64", "f32", "split_bf16"):
+        d = np.diag(phi)
+        assert np.all(np.abs(np.delete(d, 7) - 1.0) <= 10 * TOL[prec])
+
+
+def test_scaling_hetero_ref_and_batched(gpu):
+    import torch
+    m, n1, n2 = 17, 200, 90
+    S1, S2 = _rand(m, n1, 92), _rand(m, n2, 93) * 50.0
+    r1 = S1[2] + 0.01
+    phi_o, psi_o = oracle.corr2d(S1, S2, ref1=r1, alpha=0.7)
+    phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), ref1=_t(r1, gpu), prec="split_bf16", alpha=0.7)
+    assert rel_fro(_np(phi), phi_o) <= TOL["split_bf16"]
+    assert rel_fro(_np(psi), psi_o) <= TOL["split_bf16"]
+    # batched plan: every data set scaled with its own sigma
+    sets = [_rand(11, 150, 94) * 3.0, _rand(40, 260, 95), _rand(8, 70, 96) * 0.01]
+    offs, ooffs, cur, ocur = [], [], 0, 0
+    for S in sets:
+        offs.append(cur)
+        ooffs.append(ocur)
+        cur += S.size
+        ocur += S.shape[1] * (S.shape[1] + 1) // 2
+    y = torch.cat([_t(S, gpu).reshape(-1) for S in sets])
+    d = B.corr2d_desc_init(prec="f32", out_layout="upper_packed", scale_alpha=1.0)
+    plan = B.Plan(d, items=[(S.shape[0], S.shape[1], o, 0, oo) for S, o, oo in zip(sets, offs, ooffs)])
+    ph = torch.zeros(ocur, dtype=torch.float32, device=gpu)
+    ps = torch.zeros(ocur, dtype=torch.float32, device=gpu)
+    ws = plan.workspace(gpu)
+    B.corr2d_batched(plan.handle, y, ph, ps, ws)
+    gp, gq = _np(ph), _np(ps)
+    for S, oo in zip(sets, ooffs):
+        n = S.shape[1]
+        po, qo = oracle.corr2d(S, alpha=1.0)
+        P = unpack_upper(gp[oo:oo + n * (n + 1) // 2], n)
+        Q = unpack_upper(gq[oo:oo + n * (n + 1) // 2], n)
+        iu = np.triu_indices(n)
+        assert rel_fro(P[iu], po[iu]) <= TOL["f32"]
+        assert rel_fro(Q[iu], qo[iu]) <= TOL["f32"]
