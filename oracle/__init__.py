@@ -20,6 +20,9 @@ marshals numpy arrays and combines the paper's normalization readings:
   the paper's default ``Norm``; "custom" cF = ``norm_value``.  Since the
   weighted Fourier sum of real data is m times the time-domain sum (Parseval),
   the direct route under norm cF is the "noda" result times cF*m*(m-1).
+* ``hilbert="r_compat"``: the Fourier route exactly as the R code of Sec. 4.2
+  evaluates it -- the bin list (1..m-1) %/% 2 with its repeats (DC once,
+  the top bin once for odd m, the Nyquist bin of even m left out).
 * Scaling ``alpha`` (Sec. 2 Eqs. (stdev), (scalesyn), (scaleasyn)): the result
   divided by (sigma_1 sigma_2)^alpha, sigma per spectral variable from the
   dynamic spectra in use; a variable with sigma = 0 is left unscaled.
@@ -182,6 +185,27 @@ def corr_ft_circular(Y1, Y2, cF):
     return phi, psi
 
 
+def r_bins(m):
+    """Bins the R code of Sec. 4.2 keeps from each m-point FFT: with R's
+    precedence ``1:(m-1) %/% 2 + 1`` is (1..m-1) integer-divided by 2, plus 1
+    (1-based), i.e. 0-based bins floor(j/2) for j = 1..m-1, repeats kept."""
+    return np.array([j // 2 for j in range(1, m)], dtype=np.int64)
+
+
+def corr_ft_r(Y1, Y2, cF):
+    """The R package's Fourier route as printed (Sec. 4.2): cF times the sum,
+    over the bin list r_bins(m) with its repeats, of F1(bin) conj(F2(bin)),
+    F the m-point DFT of each dynamic spectrum; real part Phi, imaginary Psi."""
+    m = np.asarray(Y1).shape[0]
+    F1 = dft(Y1)
+    F2 = F1 if Y2 is Y1 else dft(Y2)
+    C = np.zeros((F1.shape[1], F2.shape[1]), dtype=np.complex128)
+    for b in r_bins(m):
+        C += np.outer(F1[b], np.conj(F2[b]))
+    C *= cF
+    return C.real.copy(), C.imag.copy()
+
+
 def corr_ft_circular_entries(Y1, Y2, cF, rows, cols):
     Y1, Y2 = _f64(Y1), _f64(Y2)
     m, n1 = Y1.shape
@@ -260,6 +284,8 @@ def corr2d(S1, S2=None, ref1=None, ref2=None, hilbert="noda", norm="noda", norm_
             psi = psi * f
     elif hilbert == "circular":
         phi, psi = corr_ft_circular(Y1, Y2, cF)
+    elif hilbert == "r_compat":
+        phi, psi = corr_ft_r(Y1, Y2 if S2 is not None else Y1, cF)
     else:
         raise ValueError(hilbert)
     if alpha != 0.0:
@@ -284,6 +310,15 @@ def corr2d_entries(S1, rows, cols, S2=None, ref1=None, ref2=None, hilbert="noda"
             psi = psi * f
     elif hilbert == "circular":
         phi, psi = corr_ft_circular_entries(Y1, Y2, cF, rows, cols)
+    elif hilbert == "r_compat":
+        rows, cols = np.asarray(rows), np.asarray(cols)
+        F1 = dft(Y1)
+        F2 = F1 if S2 is None else dft(Y2)
+        c = np.zeros(len(rows), dtype=np.complex128)
+        for b in r_bins(m):
+            c += F1[b][rows] * np.conj(F2[b][cols])
+        c *= cF
+        phi, psi = c.real.copy(), c.imag.copy()
     else:
         raise ValueError(hilbert)
     if alpha != 0.0:

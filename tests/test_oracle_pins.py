@@ -407,3 +407,53 @@ def test_scaling_general_alpha_and_zero_variance():
     pe, qe = oracle.corr2d_entries(S, i, j, alpha=a, hilbert="circular", norm="paper")
     pf, qf = oracle.corr2d(S, alpha=a, hilbert="circular", norm="paper")
     assert np.allclose(pe, pf[i, j], rtol=1e-13) and np.allclose(qe, qf[i, j], rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# R-compatible bin list (Sec. 4.2 code): floor(j/2), j = 1..m-1
+# --------------------------------------------------------------------------
+def test_r_bins_multiset():
+    # DC once, interior bins twice; odd m: top bin once; even m: no Nyquist
+    assert list(oracle.r_bins(2)) == [0]
+    assert list(oracle.r_bins(5)) == [0, 1, 1, 2]
+    assert list(oracle.r_bins(6)) == [0, 1, 1, 2, 2]
+    for m in range(2, 40):
+        b = oracle.r_bins(m)
+        cnt = np.bincount(b, minlength=m)
+        assert cnt[0] == 1 and len(b) == m - 1
+        top = (m - 1) // 2
+        for k in range(1, top):
+            assert cnt[k] == 2
+        if m > 2:
+            assert cnt[top] == (2 if m % 2 == 0 else 1)
+        if m % 2 == 0:
+            assert cnt[m // 2] == 0
+
+
+def test_r_compat_m2_is_zero():
+    # m = 2 keeps only DC, which is zero for mean-centred data
+    S = np.random.default_rng(1).standard_normal((2, 9))
+    p, q = oracle.corr2d(S, hilbert="r_compat", norm="paper")
+    assert np.abs(p).max() < 1e-15 and np.abs(q).max() < 1e-15
+
+
+@pytest.mark.parametrize("m", [5, 6, 11, 16])
+def test_r_compat_against_circular(m):
+    # the R list differs from the Hermitian-complete half spectrum only in
+    # the top bin: odd m counts bin (m-1)/2 once instead of twice, even m
+    # drops the Nyquist bin (weight 1 there)
+    rng = np.random.default_rng(m)
+    S1, S2 = rng.standard_normal((m, 12)), rng.standard_normal((m, 7))
+    cF = 1.0 / (math.pi * (m - 1))
+    pr, qr = oracle.corr2d(S1, S2, hilbert="r_compat", norm="paper")
+    pc, qc = oracle.corr2d(S1, S2, hilbert="circular", norm="paper")
+    F1 = np.fft.fft(oracle.dynamic(S1)[0], axis=0)
+    F2 = np.fft.fft(oracle.dynamic(S2)[0], axis=0)
+    top = (m - 1) // 2 if m % 2 else m // 2
+    d = cF * np.outer(F1[top], np.conj(F2[top]))
+    assert np.allclose(pr, pc - d.real, atol=1e-12)
+    assert np.allclose(qr, qc - d.imag, atol=1e-12)
+    # entries agree with the full result
+    i, j = np.array([0, 3, 11]), np.array([6, 2, 0])
+    pe, qe = oracle.corr2d_entries(S1, i, j, S2=S2, hilbert="r_compat", norm="paper")
+    assert np.allclose(pe, pr[i, j], rtol=1e-13) and np.allclose(qe, qr[i, j], rtol=1e-13)
