@@ -50,11 +50,11 @@ def rel_fro(g, o):
 
 
 def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracle_vals,
-                layout="upper_packed"):
+                layout="upper_packed", alpha=0.0):
     """Time `steps` calls; returns a dict of measurements for this form."""
     out_dtype = "f64" if prec == "f64" else "f32"
     plan = B.Plan(m=m, n1=n, n2=0, prec=prec, basis=basis, out_layout=layout,
-                  in_dtype="f64", out_dtype=out_dtype)
+                  in_dtype="f64", out_dtype=out_dtype, scale_alpha=alpha)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     numel = n * (n + 1) // 2
     phi = torch.empty(numel, dtype=tdt, device=y.device)
@@ -89,7 +89,7 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     planes = {"f64": 8, "f32": 4, "split_bf16": 4, "bf16": 2, "f16": 2, "fp8_e4m3": 1}[prec]
     kernel_bytes = 2 * entries * esz + 2 * n * info.k_pad * planes
     res = {
-        "prec": prec, "basis": basis,
+        "prec": prec, "basis": basis, "scale_alpha": alpha,
         "ms_per_step": wall * 1e3 / steps,
         "entries_per_s": entries / (wall / steps),
         "kernel_ms": kernel_ms,
@@ -351,6 +351,10 @@ def main():
                             ("f64", "fourier")):
             variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, sample,
                                         oracle_vals))
+        # Pareto scaling (alpha = 0.5) of the headline form
+        pareto_vals = oracle.corr2d_entries(S, sample[0], sample[1], alpha=0.5)
+        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, sample,
+                                    pareto_vals, alpha=0.5))
 
     workloads = []
     if not args.no_workloads:

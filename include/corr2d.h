@@ -22,6 +22,9 @@
  * CORR2D_HILBERT_CIRCULAR takes the imaginary part of the m-point half
  * spectrum product literally (the discrete Fourier route of Eq. (disint2d));
  * for finite m it differs from Noda's kernel.  Phi is the same in both.
+ * CORR2D_HILBERT_R_COMPAT evaluates the m-point route over the bin list of
+ * the package's R code (Sec. 4.2), which weighs the top bin differently
+ * (Phi differs too); with CORR2D_NORM_PAPER it reproduces that code.
  *
  * Normalization.  The factor cF multiplies the Hermitian-weighted Fourier sum
  * sum_w weight(w) F1(w) conj(F2(w)) (weight 1 for DC and Nyquist, 2 else):
@@ -83,7 +86,14 @@ typedef enum corr2d_prec {
  * Psi up to rounding; they differ in how rounding errors of reduced precisions
  * accumulate.                                                                 */
 typedef enum corr2d_basis { CORR2D_BASIS_FOURIER = 0, CORR2D_BASIS_TIME = 1 } corr2d_basis;
-typedef enum corr2d_hilbert { CORR2D_HILBERT_NODA = 0, CORR2D_HILBERT_CIRCULAR = 1 } corr2d_hilbert;
+typedef enum corr2d_hilbert {
+    CORR2D_HILBERT_NODA = 0,      /* Noda's matrix, Eq. (HilbNoda)                   */
+    CORR2D_HILBERT_CIRCULAR = 1,  /* m-point route, Hermitian-complete half spectrum */
+    CORR2D_HILBERT_R_COMPAT = 2   /* m-point route with the bin list of the package's
+                                     R code (Sec. 4.2): bins floor(j/2), j = 1..m-1
+                                     (DC once, top bin once for odd m, no Nyquist
+                                     bin for even m); Fourier basis only            */
+} corr2d_hilbert;
 typedef enum corr2d_norm { CORR2D_NORM_NODA = 0, CORR2D_NORM_PAPER = 1, CORR2D_NORM_CUSTOM = 2 } corr2d_norm;
 typedef enum corr2d_layout { CORR2D_LAYOUT_FULL = 0, CORR2D_LAYOUT_UPPER_PACKED = 1 } corr2d_layout;
 typedef enum corr2d_dtype { CORR2D_DTYPE_F64 = 0, CORR2D_DTYPE_F32 = 1 } corr2d_dtype;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcorr2d.so")
 OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EDEVICE, ENOMEM = range(6)
 PREC = {"f64": 0, "f32": 1, "split_bf16": 2, "bf16": 3, "f16": 4, "fp8_e4m3": 5}
 BASIS = {"fourier": 0, "time": 1}
-HILBERT = {"noda": 0, "circular": 1}
+HILBERT = {"noda": 0, "circular": 1, "r_compat": 2}
 NORM = {"noda": 0, "paper": 1, "custom": 2}
 LAYOUT = {"full": 0, "upper_packed": 1}
 DTYPE = {"f64": 0, "f32": 1}

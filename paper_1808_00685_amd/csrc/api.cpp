@@ -162,7 +162,9 @@ corr2d_status check_common(const corr2d_desc* d) {
         return fail(CORR2D_EINVAL, "in_dtype/out_dtype must be CORR2D_DTYPE_F64 or _F32");
     if (!valid_enum(d->prec, 0, 5)) return fail(CORR2D_EINVAL, "unknown prec %d", d->prec);
     if (!valid_enum(d->basis, 0, 1)) return fail(CORR2D_EINVAL, "unknown basis %d", d->basis);
-    if (!valid_enum(d->hilbert, 0, 1)) return fail(CORR2D_EINVAL, "unknown hilbert %d", d->hilbert);
+    if (!valid_enum(d->hilbert, 0, 2)) return fail(CORR2D_EINVAL, "unknown hilbert %d", d->hilbert);
+    if (d->hilbert == CORR2D_HILBERT_R_COMPAT && d->basis != CORR2D_BASIS_FOURIER)
+        return fail(CORR2D_EUNSUPPORTED, "the R-compatible bin list needs the Fourier basis");
     if (!valid_enum(d->norm_mode, 0, 2)) return fail(CORR2D_EINVAL, "unknown norm_mode %d", d->norm_mode);
     if (!valid_enum(d->out_layout, 0, 1)) return fail(CORR2D_EINVAL, "unknown out_layout %d", d->out_layout);
     if (d->norm_mode == CORR2D_NORM_CUSTOM && !std::isfinite(d->norm_value))

@@ -193,17 +193,28 @@ __device__ inline double qn_entry(const TwiddleView tw, const double* h, int64_t
     return sg * s;
 }
 
+// Row factor of the R code's bin list (Sec. 4.2: bins floor(j/2) for
+// j = 1..m-1) relative to the Hermitian-complete packing: the pair of the top
+// bin (m-1)/2 of an odd m counts once instead of twice (1/sqrt2 on both of
+// its rows), the Nyquist row of an even m not at all.
+__device__ inline double r_compat_row(int64_t m, int64_t r) {
+    if ((m & 1) == 0) return r == m - 1 ? 0.0 : 1.0;
+    return (m > 1 && (r == m - 2 || r == m - 1)) ? M_SQRT1_2 : 1.0;
+}
+
 __device__ inline double table_entry(const TableJob& T, const TwiddleView tw, const double* h,
                                      int64_t r, int64_t j) {
     const int64_t m = T.m;
     if (j >= m) return 0.0;
     if (r < T.kp) {
         if (r >= m) return 0.0;
+        if (T.hilbert == H_R_COMPAT) return qrow(tw, r, j) * r_compat_row(m, r);
         return T.basis == B_FOURIER ? qrow(tw, r, j) : (r == j ? 1.0 : 0.0);
     }
     const int64_t k = r - T.kp;
     if (k >= m || r >= 2 * (int64_t)T.kp) return 0.0;
     if (T.basis == B_FOURIER) {
+        if (T.hilbert == H_R_COMPAT) return jqrow(tw, k, j) * r_compat_row(m, k);
         if (T.hilbert == H_CIRCULAR) return jqrow(tw, k, j);
         // (Q N)[k][j] = sum_{l != j} Q[k][l] / (pi (j - l))
         return qn_entry(tw, h, k, j);

@@ -121,6 +121,9 @@ def _plan_status(**kw):
     (dict(prec=1, tile=3), B.EUNSUPPORTED),
     (dict(prec=2, tile=3), B.OK),
     (dict(scale_alpha=float("nan")), B.EINVAL),
+    (dict(hilbert=2, basis=1), B.EUNSUPPORTED),
+    (dict(hilbert=3), B.EINVAL),
+    (dict(hilbert=2), B.OK),
     (dict(scale_alpha=float("inf")), B.EINVAL),
     (dict(scale_alpha=0.5), B.OK),
     (dict(m=5000), B.EUNSUPPORTED),

@@ -295,3 +295,31 @@ def test_scaling_hetero_ref_and_batched(gpu):
         iu = np.triu_indices(n)
         assert rel_fro(P[iu], po[iu]) <= TOL["f32"]
         assert rel_fro(Q[iu], qo[iu]) <= TOL["f32"]
+
+
+# --------------------------------------------------------------------------
+# The R code's bin list (Sec. 4.2) with the paper's norm
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"])
+@pytest.mark.parametrize("m", [2, 3, 16, 37])
+def test_r_compat_parity(gpu, prec, m):
+    n = 150
+    S = _rand(m, n, 300 + m)
+    phi_o, psi_o = oracle.corr2d(S, hilbert="r_compat", norm="paper")
+    phi, psi, _ = _homo(S, gpu, prec=prec, hilbert="r_compat", norm="paper")
+    if m == 2:   # only DC is kept, and it is zero after centring
+        assert np.abs(phi).max() < 1e-6 and np.abs(psi).max() < 1e-6
+        return
+    check_homo_structure(phi, psi)
+    assert rel_fro(phi, phi_o) <= TOL[prec]
+    assert rel_fro(psi, psi_o) <= TOL[prec]
+
+
+def test_r_compat_hetero_and_scaled(gpu):
+    m, n1, n2 = 24, 130, 70
+    S1, S2 = _rand(m, n1, 310), _rand(m, n2, 311) * 4.0
+    phi_o, psi_o = oracle.corr2d(S1, S2, hilbert="r_compat", norm="paper", alpha=0.5)
+    phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), prec="split_bf16", hilbert="r_compat",
+                              norm="paper", alpha=0.5)
+    assert rel_fro(_np(phi), phi_o) <= TOL["split_bf16"]
+    assert rel_fro(_np(psi), psi_o) <= TOL["split_bf16"]
