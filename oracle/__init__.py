@@ -23,6 +23,9 @@ marshals numpy arrays and combines the paper's normalization readings:
 * ``hilbert="r_compat"``: the Fourier route exactly as the R code of Sec. 4.2
   evaluates it -- the bin list (1..m-1) %/% 2 with its repeats (DC once,
   the top bin once for odd m, the Nyquist bin of even m left out).
+* ``interpolate`` (Sec. 4.1): spectra resampled on N equidistant perturbation
+  values, piecewise linear or with the FMM cubic spline (the default method of
+  R's splinefun, which the paper names as the default interpolation).
 * Scaling ``alpha`` (Sec. 2 Eqs. (stdev), (scalesyn), (scaleasyn)): the result
   divided by (sigma_1 sigma_2)^alpha, sigma per spectral variable from the
   dynamic spectra in use; a variable with sigma = 0 is left unscaled.
@@ -245,6 +248,73 @@ def norm_factor(m, norm="noda", norm_value=None):
     if norm == "custom":
         return float(norm_value)
     raise ValueError(norm)
+
+
+def fmm_spline_second_derivatives(x, y):
+    """Second derivatives M at the knots of the cubic spline through (x, y)
+    with Forsythe-Malcolm-Moler end conditions: the spline's third derivative
+    on the first (last) interval equals that of the cubic through the first
+    (last) four points, 6 times their third divided difference.  Two points
+    give the straight line (M = 0), three the parabola through them.  Solved
+    as a dense linear system in FP64 (the plain definition)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = len(x)
+    if n < 3:
+        return np.zeros(n)
+    h = np.diff(x)
+    d = np.diff(y) / h
+    A = np.zeros((n, n))
+    r = np.zeros(n)
+    for i in range(1, n - 1):
+        A[i, i - 1] = h[i - 1]
+        A[i, i] = 2.0 * (h[i - 1] + h[i])
+        A[i, i + 1] = h[i]
+        r[i] = 6.0 * (d[i] - d[i - 1])
+    if n == 3:
+        third_l = third_r = 0.0
+    else:
+        def dd3(xs, ys):
+            d1 = np.diff(ys) / np.diff(xs)
+            d2 = np.diff(d1) / (xs[2:] - xs[:-2])
+            return (d2[1] - d2[0]) / (xs[3] - xs[0])
+        third_l = 6.0 * dd3(x[:4], y[:4])
+        third_r = 6.0 * dd3(x[-4:], y[-4:])
+    # (M1 - M0)/h0 = third_l, (M[n-1] - M[n-2])/h[n-2] = third_r
+    A[0, 0], A[0, 1], r[0] = -1.0, 1.0, third_l * h[0]
+    A[n - 1, n - 2], A[n - 1, n - 1], r[n - 1] = -1.0, 1.0, third_r * h[-1]
+    return np.linalg.solve(A, r)
+
+
+def fmm_spline_eval(x, y, M, t):
+    """Value at t of the cubic spline with knots x, values y and second
+    derivatives M (t inside [x0, x_last])."""
+    x = np.asarray(x, dtype=np.float64)
+    i = np.clip(np.searchsorted(x, t, side="right") - 1, 0, len(x) - 2)
+    h = x[i + 1] - x[i]
+    a, b = x[i + 1] - t, t - x[i]
+    return (M[i] * a ** 3 / (6 * h) + M[i + 1] * b ** 3 / (6 * h) +
+            (y[i] / h - M[i] * h / 6) * a + (y[i + 1] / h - M[i + 1] * h / 6) * b)
+
+
+def interpolate(S, t_in, N, method="spline"):
+    """Spectra on N equidistant perturbation values over [min t, max t]
+    (Sec. 4.1: seq(min(Time), max(Time), length.out = N), then each spectral
+    variable interpolated along t): method "linear" (piecewise linear) or
+    "spline" (the FMM cubic spline).  t_in strictly increasing."""
+    S = np.asarray(S, dtype=np.float64)
+    t_in = np.asarray(t_in, dtype=np.float64)
+    T = np.linspace(t_in[0], t_in[-1], int(N))
+    out = np.empty((len(T), S.shape[1]))
+    for c in range(S.shape[1]):
+        if method == "linear":
+            out[:, c] = np.interp(T, t_in, S[:, c])
+        elif method == "spline":
+            M = fmm_spline_second_derivatives(t_in, S[:, c])
+            out[:, c] = fmm_spline_eval(t_in, S[:, c], M, T)
+        else:
+            raise ValueError(method)
+    return out
 
 
 def band_sd(Y):

@@ -457,3 +457,64 @@ def test_r_compat_against_circular(m):
     i, j = np.array([0, 3, 11]), np.array([6, 2, 0])
     pe, qe = oracle.corr2d_entries(S1, i, j, S2=S2, hilbert="r_compat", norm="paper")
     assert np.allclose(pe, pr[i, j], rtol=1e-13) and np.allclose(qe, qr[i, j], rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Interpolation to equidistant perturbation values (Sec. 4.1)
+# --------------------------------------------------------------------------
+def _uneven_t(m, seed):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.uniform(0.2, 2.0, size=m)) - 0.7
+
+
+def test_spline_reproduces_cubics_exactly():
+    # the FMM end conditions are exact for cubics, so the spline of cubic
+    # data is that cubic everywhere
+    t = _uneven_t(9, 1)
+    coef = np.array([0.3, -1.2, 0.7, 0.05])
+    f = lambda x: np.polyval(coef[::-1], x)
+    S = np.stack([f(t), 2.0 * f(t) - 1.0], axis=1)
+    out = oracle.interpolate(S, t, 31, "spline")
+    T = np.linspace(t[0], t[-1], 31)
+    assert np.allclose(out[:, 0], f(T), rtol=1e-12, atol=1e-11)
+    assert np.allclose(out[:, 1], 2.0 * f(T) - 1.0, rtol=1e-12, atol=1e-11)
+
+
+def test_spline_end_condition_and_knots():
+    t = _uneven_t(12, 2)
+    y = np.sin(t) + 0.1 * t * t
+    M = oracle.fmm_spline_second_derivatives(t, y)
+    h = np.diff(t)
+    c4 = np.polyfit(t[:4], y[:4], 3)           # cubic through the first four points
+    assert abs((M[1] - M[0]) / h[0] - 6 * c4[0]) < 1e-9
+    c4r = np.polyfit(t[-4:], y[-4:], 3)
+    assert abs((M[-1] - M[-2]) / h[-1] - 6 * c4r[0]) < 1e-9
+    # interpolates the knots, continuous first derivative at interior knots
+    assert np.allclose(oracle.fmm_spline_eval(t, y, M, t), y, atol=1e-13)
+    eps = 1e-7
+    for i in range(1, len(t) - 1):
+        dl = (oracle.fmm_spline_eval(t, y, M, t[i]) - oracle.fmm_spline_eval(t, y, M, t[i] - eps)) / eps
+        dr = (oracle.fmm_spline_eval(t, y, M, t[i] + eps) - oracle.fmm_spline_eval(t, y, M, t[i])) / eps
+        assert abs(dl - dr) < 1e-5
+
+
+def test_interpolation_small_cases_and_linear():
+    # two points: a line; three points: the parabola through them
+    t2, t3 = np.array([0.0, 2.0]), np.array([0.0, 1.0, 3.0])
+    y3 = np.array([1.0, 2.0, 0.5])
+    T = np.linspace(0.0, 3.0, 7)
+    par = np.polyfit(t3, y3, 2)
+    assert np.allclose(oracle.interpolate(y3[:, None], t3, 7, "spline")[:, 0], np.polyval(par, T), atol=1e-12)
+    assert np.allclose(oracle.interpolate(np.array([[1.0], [5.0]]), t2, 5, "spline")[:, 0],
+                       np.linspace(1.0, 5.0, 5), atol=1e-13)
+    # piecewise linear: exact for lines, and the knots are kept when the
+    # target grid contains them
+    t = _uneven_t(8, 3)
+    S = np.stack([3.0 * t - 2.0, -t], axis=1)
+    T = np.linspace(t[0], t[-1], 20)
+    out = oracle.interpolate(S, t, 20, "linear")
+    assert np.allclose(out, np.stack([3.0 * T - 2.0, -T], axis=1), atol=1e-12)
+    te = np.linspace(0.0, 1.0, 6)
+    Se = np.random.default_rng(4).standard_normal((6, 3))
+    for meth in ("linear", "spline"):
+        assert np.allclose(oracle.interpolate(Se, te, 6, meth), Se, atol=1e-13)
