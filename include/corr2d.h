@@ -131,7 +131,29 @@ typedef struct corr2d_desc {
                            1 = Pearson, 0.5 = Pareto.  sigma per spectral
                            variable from the dynamic spectrum in use; a
                            variable with sigma = 0 stays unscaled.  Finite.     */
+    /* Interpolation to equidistant perturbation values (Sec. 4.1).  With
+     * interp != CORR2D_INTERP_NONE the input spectra have m_in rows taken at
+     * the perturbation values t_in[0..m_in-1] (host memory, strictly
+     * increasing, read when the plan is made); each spectral variable is
+     * resampled on the m equidistant values t_in[0] + k (t_in[m_in-1] -
+     * t_in[0]) / (m-1), in FP64, before the correlation.  Not for batched
+     * plans.                                                                  */
+    const double* t_in;
+    int64_t m_in;
+    int32_t interp;     /* corr2d_interp                                          */
+    int32_t reserved2;
 } corr2d_desc;
+
+/* Interpolation of Sec. 4.1: piecewise linear (R's approxfun), or the cubic
+ * spline with the end conditions of Forsythe, Malcolm and Moler (the default
+ * method of R's splinefun): end third derivatives equal those of the cubics
+ * through the first and last four points; three points give the parabola
+ * through them, two the line.                                                 */
+typedef enum corr2d_interp {
+    CORR2D_INTERP_NONE = 0,
+    CORR2D_INTERP_LINEAR = 1,
+    CORR2D_INTERP_SPLINE = 2
+} corr2d_interp;
 
 /* One data set of a batched homocorrelation.  Offsets are in elements from
  * the base pointers given to corr2d_batched.                                   */

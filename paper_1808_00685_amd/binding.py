@@ -19,6 +19,7 @@ OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EDEVICE, ENOMEM = range(6)
 PREC = {"f64": 0, "f32": 1, "split_bf16": 2, "bf16": 3, "f16": 4, "fp8_e4m3": 5}
 BASIS = {"fourier": 0, "time": 1}
 HILBERT = {"noda": 0, "circular": 1, "r_compat": 2}
+INTERP = {"none": 0, "linear": 1, "spline": 2}
 NORM = {"noda": 0, "paper": 1, "custom": 2}
 LAYOUT = {"full": 0, "upper_packed": 1}
 DTYPE = {"f64": 0, "f32": 1}
@@ -44,6 +45,8 @@ class corr2d_desc(ctypes.Structure):
         ("norm_value", ctypes.c_double), ("out_layout", ctypes.c_int32),
         ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("scale_alpha", ctypes.c_double),
+        ("t_in", ctypes.POINTER(ctypes.c_double)), ("m_in", ctypes.c_int64),
+        ("interp", ctypes.c_int32), ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -160,8 +163,20 @@ def corr2d_desc_init(**fields) -> corr2d_desc:
     d = corr2d_desc()
     lib().corr2d_desc_init(ctypes.byref(d))
     maps = {"prec": PREC, "basis": BASIS, "hilbert": HILBERT, "norm_mode": NORM,
-            "out_layout": LAYOUT, "in_dtype": DTYPE, "out_dtype": DTYPE}
+            "out_layout": LAYOUT, "in_dtype": DTYPE, "out_dtype": DTYPE, "interp": INTERP}
     for k, v in fields.items():
+        if k == "t_in":
+            # perturbation values of the input rows (read when the plan is
+            # made); the array stays referenced by the descriptor
+            if v is None:
+                continue
+            import numpy as np
+            arr = np.ascontiguousarray(v, dtype=np.float64)
+            d._t_in_ref = arr
+            d.t_in = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            if "m_in" not in fields:
+                d.m_in = len(arr)
+            continue
         if k in maps and isinstance(v, str):
             v = maps[k][v]
         setattr(d, k, v)
@@ -261,17 +276,22 @@ class Plan:
 
 
 def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="fourier",
-         hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0, stream=None):
-    """Homocorrelation of y (torch, m x n, float64/float32, on the GPU)."""
+         hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0,
+         t_in=None, interp="none", m_out=None, stream=None):
+    """Homocorrelation of y (torch, m x n, float64/float32, on the GPU).  With
+    interp "linear" or "spline", y's rows were taken at perturbation values
+    t_in and are resampled on m_out (default: as many) equidistant values."""
     import torch
     m, n = y.shape
+    if interp != "none":
+        m = m_out or m
     if out_dtype is None:
         out_dtype = "f64" if prec == "f64" else "f32"
     plan = Plan(m=m, n1=n, n2=0, ld_in1=y.stride(0),
                 in_dtype="f64" if y.dtype == torch.float64 else "f32",
                 out_dtype=out_dtype, prec=prec, basis=basis, hilbert=hilbert, norm_mode=norm,
                 norm_value=norm_value, out_layout=layout, flags=flags, tile=tile,
-                scale_alpha=alpha)
+                scale_alpha=alpha, t_in=t_in, interp=interp)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     numel = n * (n + 1) // 2 if layout == "upper_packed" else n * n
     phi = torch.empty(numel, dtype=tdt, device=y.device)
@@ -284,18 +304,23 @@ def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="f
 
 
 def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basis="fourier",
-           hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0, stream=None):
+           hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0,
+           t_in=None, interp="none", m_out=None, stream=None):
+    """Heterocorrelation of y1 (m x n1) with y2 (m x n2), both on the GPU;
+    interp, t_in, m_out as for homo()."""
     import torch
     m, n1 = y1.shape
     m2, n2 = y2.shape
     assert m == m2
+    if interp != "none":
+        m = m_out or m
     if out_dtype is None:
         out_dtype = "f64" if prec == "f64" else "f32"
     plan = Plan(m=m, n1=n1, n2=n2, ld_in1=y1.stride(0), ld_in2=y2.stride(0),
                 in_dtype="f64" if y1.dtype == torch.float64 else "f32",
                 out_dtype=out_dtype, prec=prec, basis=basis, hilbert=hilbert, norm_mode=norm,
                 norm_value=norm_value, out_layout="full", flags=flags, tile=tile,
-                scale_alpha=alpha)
+                scale_alpha=alpha, t_in=t_in, interp=interp)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     phi = torch.empty(n1, n2, dtype=tdt, device=y1.device)
     psi = torch.empty(n1, n2, dtype=tdt, device=y1.device)

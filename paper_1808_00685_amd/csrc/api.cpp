@@ -16,6 +16,7 @@
 
 #include "corr2d.h"
 #include "corr2d_internal.h"
+#include "interp.h"
 #include "launch.h"
 #include "tune.h"
 
@@ -133,6 +134,11 @@ struct corr2d_plan_s {
     size_t counter_off = 0;
     int64_t total_tiles = 0;
     int64_t out_elements = 0;
+    // interpolation onto the equidistant perturbation grid
+    bool interp = false;
+    InterpWeights iw;
+    size_t iw_off = 0, iw_bytes = 0, yi1_off = 0, yi2_off = 0;
+    void* iw_blob = nullptr;   // pinned copy of W and the block ranges (first call)
     std::mutex mu;
     // graph cache (one entry)
     struct GraphKey {
@@ -171,6 +177,17 @@ corr2d_status check_common(const corr2d_desc* d) {
         return fail(CORR2D_EINVAL, "CUSTOM norm needs a finite norm_value");
     if (!std::isfinite(d->scale_alpha))
         return fail(CORR2D_EINVAL, "scale_alpha must be finite");
+    if (!valid_enum(d->interp, 0, 2)) return fail(CORR2D_EINVAL, "unknown interp %d", d->interp);
+    if (d->interp != CORR2D_INTERP_NONE) {
+        if (!d->t_in) return fail(CORR2D_EINVAL, "interpolation needs t_in");
+        if (d->m_in < 2 || d->m_in > kMaxM)
+            return fail(CORR2D_EINVAL, "m_in = %lld out of range", (long long)d->m_in);
+        for (int64_t i = 0; i < d->m_in; ++i) {
+            if (!std::isfinite(d->t_in[i])) return fail(CORR2D_EINVAL, "t_in[%lld] is not finite", (long long)i);
+            if (i > 0 && !(d->t_in[i] > d->t_in[i - 1]))
+                return fail(CORR2D_EINVAL, "t_in must be strictly increasing (t_in[%lld])", (long long)i);
+        }
+    }
     if (d->flags & ~0xfu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
     if (d->prec == CORR2D_PREC_FP8_E4M3 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
         return fail(CORR2D_EUNSUPPORTED, "FP8 e4m3 requires per-band scaling (range 448)");
@@ -434,6 +451,25 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
         p->s2 = layout_set(p->g2, d->prec, t64, true, &off);
         p->ntiles = (p->g1.n_pad / (32 * p->tile.fm)) * (p->g2.n_pad / (32 * p->tile.fn));
     }
+    if (d->interp != CORR2D_INTERP_NONE) {
+        // weights of the resampling (FP64, host), uploaded with every call;
+        // the resampled spectra live in the workspace
+        p->interp = true;
+        p->d.t_in = nullptr;   // the plan keeps no caller pointer
+        if (!build_interp_weights(d->t_in, d->m_in, d->m, d->interp, p->iw)) {
+            delete p;
+            return fail(CORR2D_EINVAL, "interpolation weights are not finite");
+        }
+        p->iw_bytes = align256(p->iw.W.size() * sizeof(double)) + p->iw.block_range.size() * sizeof(int32_t);
+        p->iw_off = off;
+        off = align256(off + p->iw_bytes);
+        p->yi1_off = off;
+        off = align256(off + (size_t)d->m * (size_t)p->g1.n_pad * sizeof(double));
+        if (hetero) {
+            p->yi2_off = off;
+            off = align256(off + (size_t)d->m * (size_t)p->g2.n_pad * sizeof(double));
+        }
+    }
     p->ws_bytes = off;
     *out = p;
     return ok();
@@ -446,6 +482,8 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
     if (count < 1 || count > (1 << 20)) return fail(CORR2D_EINVAL, "count = %lld out of range", (long long)count);
     corr2d_status st = check_common(common);
     if (st != CORR2D_OK) return st;
+    if (common->interp != CORR2D_INTERP_NONE)
+        return fail(CORR2D_EUNSUPPORTED, "interpolation is not available for batched plans");
     for (int64_t i = 0; i < count; ++i) {
         const corr2d_item& it = items[i];
         if (it.m < 2 || it.m > kMaxM) return fail(CORR2D_EINVAL, "item %lld: m = %lld out of range", (long long)i, (long long)it.m);
@@ -538,6 +576,7 @@ corr2d_status corr2d_plan_destroy(corr2d_plan_t p) {
     if (!p) return ok();
     if (p->have_graph && p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->host_blob) hipHostFree(p->host_blob);
+    if (p->iw_blob) hipHostFree(p->iw_blob);
     delete p;
     return ok();
 }
@@ -579,6 +618,50 @@ corr2d_status corr2d_plan_get_info(corr2d_plan_t p, corr2d_plan_info* info) {
     return ok();
 }
 
+namespace {
+
+// Upload the interpolation weights (from a pinned copy made on the first
+// call) into the workspace.
+corr2d_status upload_interp(corr2d_plan_s* p, void* ws, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        if (!p->iw_blob) {
+            void* b = nullptr;
+            hipError_t e = hipHostMalloc(&b, p->iw_bytes, hipHostMallocDefault);
+            if (e != hipSuccess) return device_fail(e, "pinned interpolation weights");
+            std::memcpy(b, p->iw.W.data(), p->iw.W.size() * sizeof(double));
+            std::memcpy((char*)b + align256(p->iw.W.size() * sizeof(double)), p->iw.block_range.data(),
+                        p->iw.block_range.size() * sizeof(int32_t));
+            p->iw_blob = b;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(at<char>(ws, p->iw_off), p->iw_blob, p->iw_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return device_fail(e, "interpolation weight upload");
+    return CORR2D_OK;
+}
+
+// Resample one data set (m_in input rows) onto the equidistant grid in the
+// workspace; the centring then reads it as FP64 rows of stride n_pad.
+corr2d_status resample(const corr2d_plan_s* p, void* ws, const void* y, int64_t ld, const Geo& g,
+                       size_t out_off, hipStream_t s) {
+    InterpJob J{};
+    J.y = y;
+    J.ld = ld;
+    J.n = g.n;
+    J.m_in = p->iw.m_in;
+    J.N = p->iw.N;
+    J.in_f64 = p->d.in_dtype == CORR2D_DTYPE_F64;
+    J.W = at<double>(ws, p->iw_off);
+    J.range = (const int32_t*)(at<char>(ws, p->iw_off) + align256(p->iw.W.size() * sizeof(double)));
+    J.out = at<double>(ws, out_off);
+    J.ld_out = g.n_pad;
+    hipError_t e = launch_interp(J, s);
+    if (e != hipSuccess) return device_fail(e, "interpolation launch");
+    return CORR2D_OK;
+}
+
+}  // namespace
+
 corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, void* phi, void* psi,
                           void* ws, size_t ws_bytes, void* stream) {
     if (!p) return fail(CORR2D_EINVAL, "NULL plan");
@@ -600,8 +683,18 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
+    const void* yc = y;
+    int64_t ldc = p->d.ld_in1;
+    if (p->interp) {
+        st = upload_interp(p, ws, s);
+        if (st == CORR2D_OK) st = resample(p, ws, y, p->d.ld_in1, p->g1, p->yi1_off, s);
+        if (st != CORR2D_OK) return st;
+        yc = at<char>(ws, p->yi1_off);
+        ldc = p->g1.n_pad;
+    }
     PrepSrcInline ps{};
-    ps.j[0] = make_prep_job(p, p->g1, p->s1, y, p->d.ld_in1, ref, ws, p->table_off);
+    ps.j[0] = make_prep_job(p, p->g1, p->s1, yc, ldc, ref, ws, p->table_off);
+    if (p->interp) ps.j[0].in_f64 = 1;
     ps.count = 1;
     ps.blocks0 = center_blocks(p->g1);
     e = launch_center(ps, ps.blocks0, s);
@@ -641,9 +734,22 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
+    const void *yc1 = y1, *yc2 = y2;
+    int64_t ldc1 = p->d.ld_in1, ldc2 = p->d.ld_in2;
+    if (p->interp) {
+        st = upload_interp(p, ws, s);
+        if (st == CORR2D_OK) st = resample(p, ws, y1, p->d.ld_in1, p->g1, p->yi1_off, s);
+        if (st == CORR2D_OK) st = resample(p, ws, y2, p->d.ld_in2, p->g2, p->yi2_off, s);
+        if (st != CORR2D_OK) return st;
+        yc1 = at<char>(ws, p->yi1_off);
+        yc2 = at<char>(ws, p->yi2_off);
+        ldc1 = p->g1.n_pad;
+        ldc2 = p->g2.n_pad;
+    }
     PrepSrcInline ps{};
-    ps.j[0] = make_prep_job(p, p->g1, p->s1, y1, p->d.ld_in1, ref1, ws, p->table_off);
-    ps.j[1] = make_prep_job(p, p->g2, p->s2, y2, p->d.ld_in2, ref2, ws, p->table_off);
+    ps.j[0] = make_prep_job(p, p->g1, p->s1, yc1, ldc1, ref1, ws, p->table_off);
+    ps.j[1] = make_prep_job(p, p->g2, p->s2, yc2, ldc2, ref2, ws, p->table_off);
+    if (p->interp) ps.j[0].in_f64 = ps.j[1].in_f64 = 1;
     ps.count = 2;
     ps.blocks0 = center_blocks(p->g1);
     e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);

@@ -83,6 +83,21 @@ struct PrepJob {
     double alpha;         // result scaling exponent (0: none): columns x sigma^-alpha
 };
 
+// Resampling of one data set onto the equidistant perturbation grid: out =
+// W y (FP64), W N x m_in; range[2b], range[2b+1] bound the nonzero input rows
+// of output rows [b kInterpRows, (b+1) kInterpRows).
+constexpr int kInterpRows = 64;
+struct InterpJob {
+    const void* y;        // m_in x ld input spectra (device)
+    int64_t ld, n, m_in, N;
+    int32_t in_f64;       // 1: y is double, 0: float
+    int32_t pad0;
+    const double* W;      // N x m_in (workspace)
+    const int32_t* range; // (workspace)
+    double* out;          // N x ld_out (workspace)
+    int64_t ld_out;
+};
+
 // One correlation contraction (a homocorrelation or a heterocorrelation).
 struct CorrJob {
     const void* L0; const void* L1;   // left operand planes (set 1, A)

@@ -1289,8 +1289,60 @@ __global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* job
 }
 
 // =========================================================================
+// Interpolation onto the equidistant perturbation grid (FP64)
+// =========================================================================
+// Workgroup: 64 spectral points x 64 output rows; thread (c, s) owns output
+// rows s, s+4, ... of column c.  The weights of the block's rows are staged
+// through LDS in chunks of 64 input rows (read by a whole wave at once, a
+// broadcast); only the block's nonzero input rows are visited.
+__device__ inline double interp_load(const InterpJob& J, int64_t i, int64_t col) {
+    return J.in_f64 ? ((const double*)J.y)[i * J.ld + col] : (double)((const float*)J.y)[i * J.ld + col];
+}
+
+__global__ __launch_bounds__(256) void interp_kernel(InterpJob J) {
+    __shared__ double Wl[kInterpRows][64 + 1];
+    const int tid = threadIdx.x, cl = tid & 63, rs = tid >> 6;
+    const int64_t col = (int64_t)blockIdx.x * 64 + cl;
+    const int64_t k0 = (int64_t)blockIdx.y * kInterpRows;
+    const int lo = J.range[2 * blockIdx.y], hi = J.range[2 * blockIdx.y + 1];
+    double acc[kInterpRows / 4];
+#pragma unroll
+    for (int q = 0; q < kInterpRows / 4; ++q) acc[q] = 0.0;
+    for (int i0 = lo; i0 < hi; i0 += 64) {
+        __syncthreads();   // previous chunk's readers are done
+        for (int e = tid; e < kInterpRows * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;
+            const int64_t k = k0 + r, i = i0 + c;
+            Wl[r][c] = (k < J.N && i < hi) ? J.W[k * J.m_in + i] : 0.0;
+        }
+        __syncthreads();
+        const int ie = hi - i0 < 64 ? hi - i0 : 64;
+        if (col < J.n) {
+            for (int ii = 0; ii < ie; ++ii) {
+                const double y = interp_load(J, i0 + ii, col);
+#pragma unroll
+                for (int q = 0; q < kInterpRows / 4; ++q) acc[q] += Wl[rs + 4 * q][ii] * y;
+            }
+        }
+    }
+    if (col < J.n) {
+#pragma unroll
+        for (int q = 0; q < kInterpRows / 4; ++q) {
+            const int64_t k = k0 + rs + 4 * q;
+            if (k < J.N) J.out[k * J.ld_out + col] = acc[q];
+        }
+    }
+}
+
+// =========================================================================
 // Host launchers
 // =========================================================================
+hipError_t launch_interp(const InterpJob& J, hipStream_t s) {
+    const dim3 grid((unsigned)((J.n + 63) / 64), (unsigned)((J.N + kInterpRows - 1) / kInterpRows));
+    hipLaunchKernelGGL(interp_kernel, grid, dim3(256), 0, s, J);
+    return hipGetLastError();
+}
+
 hipError_t launch_tables(const TableSrcInline& src, int blocks, int64_t max_m, hipStream_t s) {
     hipLaunchKernelGGL(tables_kernel<TableSrcInline>, dim3(blocks), dim3(256), (size_t)(32 * max_m), s, src);
     return hipGetLastError();

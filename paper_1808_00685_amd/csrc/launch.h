@@ -84,5 +84,6 @@ hipError_t launch_corr_persistent(int prec, int fm, int fn, bool out_f64, const 
                                   int* counter, int blocks, hipStream_t s);
 int corr_variant_supported(int prec, int fm, int fn);
 int persistent_blocks_per_cu(int prec, int fm, int fn, bool out_f64);
+hipError_t launch_interp(const InterpJob& J, hipStream_t s);
 
 }  // namespace corr2d

@@ -8,6 +8,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_1808_00685_amd import binding as B
@@ -63,8 +64,9 @@ def test_struct_layout_matches_binding():
 #include <stddef.h>
 #include "corr2d.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu %zu\n", sizeof(corr2d_desc), offsetof(corr2d_desc, norm_value),
-        offsetof(corr2d_desc, tile), offsetof(corr2d_desc, scale_alpha), sizeof(corr2d_item),
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(corr2d_desc), offsetof(corr2d_desc, norm_value),
+        offsetof(corr2d_desc, tile), offsetof(corr2d_desc, scale_alpha),
+        offsetof(corr2d_desc, t_in), offsetof(corr2d_desc, interp), sizeof(corr2d_item),
         sizeof(corr2d_plan_info));
  return 0;}
 '''
@@ -77,6 +79,7 @@ int main(void){
         vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert vals == [ctypes.sizeof(B.corr2d_desc), B.corr2d_desc.norm_value.offset,
                     B.corr2d_desc.tile.offset, B.corr2d_desc.scale_alpha.offset,
+                    B.corr2d_desc.t_in.offset, B.corr2d_desc.interp.offset,
                     ctypes.sizeof(B.corr2d_item), ctypes.sizeof(B.corr2d_plan_info)]
 
 
@@ -124,6 +127,13 @@ def _plan_status(**kw):
     (dict(hilbert=2, basis=1), B.EUNSUPPORTED),
     (dict(hilbert=3), B.EINVAL),
     (dict(hilbert=2), B.OK),
+    (dict(interp=3), B.EINVAL),
+    (dict(interp=1), B.EINVAL),                                   # no t_in
+    (dict(interp=1, t_in=[0.0, 1.0, 1.0, 2.0]), B.EINVAL),       # not increasing
+    (dict(interp=2, t_in=[0.0, float("nan"), 2.0]), B.EINVAL),
+    (dict(interp=2, t_in=[1.0]), B.EINVAL),                       # m_in = 1
+    (dict(interp=2, t_in=[0.0, 0.5, 2.0, 2.2, 4.0]), B.OK),
+    (dict(interp=1, t_in=[0.0, 3.0]), B.OK),
     (dict(scale_alpha=float("inf")), B.EINVAL),
     (dict(scale_alpha=0.5), B.OK),
     (dict(m=5000), B.EUNSUPPORTED),
@@ -206,3 +216,17 @@ def test_batched_plan_validation_and_sizes():
     assert s == B.EINVAL and not h
     s, h = B.corr2d_batched_plan(d, [(10, 300, -1, 0, 0)], check=False)
     assert s == B.EINVAL
+
+
+def test_interpolation_plan_workspace_and_batched_rejected():
+    base = dict(m=16, n1=300, prec="f32")
+    _, h0 = B.corr2d_plan(B.corr2d_desc_init(**base))
+    _, h1 = B.corr2d_plan(B.corr2d_desc_init(interp="spline", t_in=np.linspace(0.0, 1.0, 11) ** 1.5,
+                                             **base))
+    # resampled spectra (16 x n_pad FP64) and weights (16 x 11) live in the workspace
+    assert B.corr2d_workspace_bytes(h1) >= B.corr2d_workspace_bytes(h0) + 16 * 300 * 8 + 16 * 11 * 8
+    B.corr2d_plan_destroy(h0)
+    B.corr2d_plan_destroy(h1)
+    d = B.corr2d_desc_init(prec="f32", interp="linear", t_in=[0.0, 1.0, 3.0])
+    s, _ = B.corr2d_batched_plan(d, [(3, 100, 0, 0, 0)], check=False)
+    assert s == B.EUNSUPPORTED

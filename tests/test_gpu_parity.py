@@ -323,3 +323,49 @@ def test_r_compat_hetero_and_scaled(gpu):
                               norm="paper", alpha=0.5)
     assert rel_fro(_np(phi), phi_o) <= TOL["split_bf16"]
     assert rel_fro(_np(psi), psi_o) <= TOL["split_bf16"]
+
+
+# --------------------------------------------------------------------------
+# Interpolation to equidistant perturbation values (Sec. 4.1)
+# --------------------------------------------------------------------------
+def _uneven(m_in, seed):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.uniform(0.3, 2.5, size=m_in))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "bf16"])
+@pytest.mark.parametrize("method", ["linear", "spline"])
+@pytest.mark.parametrize("m_in,m_out", [(20, 32), (2, 9), (3, 8), (70, 64)])
+def test_interpolation_parity(gpu, prec, method, m_in, m_out):
+    n = 210
+    t = _uneven(m_in, 400 + m_in)
+    S = _rand(m_in, n, 401 + m_in)
+    Si = oracle.interpolate(S, t, m_out, method)
+    phi_o, psi_o = oracle.corr2d(Si)
+    phi, psi, plan = _homo(S, gpu, prec=prec, interp=method, t_in=t, m_out=m_out)
+    assert rel_fro(phi, phi_o) <= TOL[prec]
+    if m_in == 2:
+        # two input rows: every resampled column follows the same straight
+        # line in t, so Psi = b_i b_j x^T N x vanishes (N antisymmetric)
+        assert np.abs(psi_o).max() <= 1e-14 * np.abs(phi_o).max()
+        assert np.abs(psi).max() <= TOL[prec] * np.abs(phi).max()
+    else:
+        assert rel_fro(psi, psi_o) <= TOL[prec]
+
+
+def test_interpolation_hetero_f32_input_scaled(gpu):
+    import torch
+    m_in, m_out = 15, 40
+    t = _uneven(m_in, 410)
+    S1, S2 = _rand(m_in, 120, 411), _rand(m_in, 90, 412) * 7.0
+    S1i, S2i = oracle.interpolate(S1, t, m_out, "spline"), oracle.interpolate(S2, t, m_out, "spline")
+    phi_o, psi_o = oracle.corr2d(S1i, S2i, alpha=0.5)
+    y1 = _t(S1, gpu, torch.float32)
+    y2 = _t(S2, gpu, torch.float32)
+    # FP32 input: compare with the oracle on the same FP32-rounded spectra
+    S1f, S2f = S1.astype(np.float32).astype(np.float64), S2.astype(np.float32).astype(np.float64)
+    phi_o, psi_o = oracle.corr2d(oracle.interpolate(S1f, t, m_out, "spline"),
+                                 oracle.interpolate(S2f, t, m_out, "spline"), alpha=0.5)
+    phi, psi, _, _ = B.hetero(y1, y2, prec="f64", interp="spline", t_in=t, m_out=m_out, alpha=0.5)
+    assert rel_fro(_np(phi), phi_o) <= 1e-12
+    assert rel_fro(_np(psi), psi_o) <= 1e-12
