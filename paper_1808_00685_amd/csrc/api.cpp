@@ -49,6 +49,27 @@ corr2d_status device_fail(hipError_t e, const char* where) {
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Job arrays of a batched call (pinned on the host, copied to the workspace).
+struct BlobLayout {
+    size_t tables, tstart, qstart, prep, cstart, xstart, corr, tilestart, total;
+};
+
+BlobLayout blob_layout(size_t nd, size_t count) {
+    BlobLayout b;
+    size_t o = 0;
+    b.tables = o; o = align256(o + nd * sizeof(TableJob));
+    b.tstart = o; o = align256(o + (nd + 1) * sizeof(int32_t));
+    b.qstart = o; o = align256(o + (nd + 1) * sizeof(int32_t));
+    b.prep = o; o = align256(o + count * sizeof(PrepJob));
+    b.cstart = o; o = align256(o + (count + 1) * sizeof(int32_t));
+    b.xstart = o; o = align256(o + (count + 1) * sizeof(int32_t));
+    b.corr = o; o = align256(o + count * sizeof(CorrJob));
+    b.tilestart = o; o = align256(o + (count + 1) * sizeof(int64_t));
+    b.total = o;
+    return b;
+}
+
+
 constexpr int64_t kMaxM = 4096;          // twiddle table limit of the table kernel
 constexpr int64_t kMaxN = (int64_t)1 << 24;
 
@@ -317,6 +338,12 @@ int transform_blocks(const Geo& g, int prec) {
 
 // Tiles of the upper triangle when a row tile is R column tiles tall: row
 // tile I pairs with column tiles J >= R I of the R T column tiles.
+// The Q N rows of the table (Fourier basis, Noda's kernel) come from their
+// own kernel.
+bool needs_qn(const corr2d_plan_s* p) {
+    return p->d.basis == CORR2D_BASIS_FOURIER && p->d.hilbert == CORR2D_HILBERT_NODA;
+}
+
 int64_t triangle_tiles(int64_t T, int64_t R) { return R * T * (T + 1) / 2; }
 
 CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1, const Geo& g2,
@@ -560,9 +587,7 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
         if (gr.tiles > best) { best = gr.tiles; p->tile = gr.tile; }
     // job arrays: tables, prep, corr, block starts, tile starts
     const size_t nd = p->distinct_m.size();
-    p->jobs_bytes = align256(nd * sizeof(TableJob)) + align256((nd + 1) * sizeof(int32_t)) +
-                    align256(count * sizeof(PrepJob)) + align256((count + 1) * sizeof(int32_t)) * 2 +
-                    align256(count * sizeof(CorrJob)) + align256((count + 1) * sizeof(int64_t));
+    p->jobs_bytes = blob_layout(nd, (size_t)count).total;
     p->jobs_off = off;
     off = align256(off + p->jobs_bytes);
     p->counter_off = off;
@@ -681,6 +706,7 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
     hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
+    if (e == hipSuccess && needs_qn(p)) e = launch_tables_qn(ts, qn_blocks(p->g1.m), p->g1.m, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     const void* yc = y;
@@ -732,6 +758,7 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
     hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
+    if (e == hipSuccess && needs_qn(p)) e = launch_tables_qn(ts, qn_blocks(p->g1.m), p->g1.m, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     const void *yc1 = y1, *yc2 = y2;
@@ -774,24 +801,6 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
 // ---------------------------------------------------------------------------
 namespace {
 
-struct BlobLayout {
-    size_t tables, tstart, prep, cstart, xstart, corr, tilestart, total;
-};
-
-BlobLayout blob_layout(size_t nd, size_t count) {
-    BlobLayout b;
-    size_t o = 0;
-    b.tables = o; o = align256(o + nd * sizeof(TableJob));
-    b.tstart = o; o = align256(o + (nd + 1) * sizeof(int32_t));
-    b.prep = o; o = align256(o + count * sizeof(PrepJob));
-    b.cstart = o; o = align256(o + (count + 1) * sizeof(int32_t));
-    b.xstart = o; o = align256(o + (count + 1) * sizeof(int32_t));
-    b.corr = o; o = align256(o + count * sizeof(CorrJob));
-    b.tilestart = o; o = align256(o + (count + 1) * sizeof(int64_t));
-    b.total = o;
-    return b;
-}
-
 // Fill the pinned host blob with the job arrays for these pointers.
 void fill_blob(corr2d_plan_s* p, const void* y_base, void* phi_base, void* psi_base, void* ws) {
     const size_t nd = p->distinct_m.size(), count = p->items.size();
@@ -808,6 +817,13 @@ void fill_blob(corr2d_plan_s* p, const void* y_base, void* phi_base, void* psi_b
         blk += table_blocks(g);
     }
     ts[nd] = blk;
+    int32_t* qs = (int32_t*)(h + L.qstart);
+    int32_t qb = 0;
+    for (size_t q = 0; q < nd; ++q) {
+        qs[q] = qb;
+        qb += qn_blocks(p->distinct_m[q]);
+    }
+    qs[nd] = qb;
     PrepJob* pj = (PrepJob*)(h + L.prep);
     int32_t* cs = (int32_t*)(h + L.cstart);
     int32_t* xs = (int32_t*)(h + L.xstart);
@@ -852,10 +868,13 @@ corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
     TableSrcArray ta{};
     ta.jobs = (const TableJob*)(dev + L.tables);
     ta.start = (const int32_t*)(dev + L.tstart);
+    ta.qstart = (const int32_t*)(dev + L.qstart);
     ta.count = (int32_t)nd;
     ta.counter = counter;
     ta.ncounters = (int32_t)p->groups.size();
-    e = launch_tables(ta, ((const int32_t*)(h + L.tstart))[nd], *std::max_element(p->distinct_m.begin(), p->distinct_m.end()), s);
+    const int64_t max_m = *std::max_element(p->distinct_m.begin(), p->distinct_m.end());
+    e = launch_tables(ta, ((const int32_t*)(h + L.tstart))[nd], max_m, s);
+    if (e == hipSuccess && needs_qn(p)) e = launch_tables_qn(ta, ((const int32_t*)(h + L.qstart))[nd], max_m, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     PrepSrcArray pa{};
@@ -899,6 +918,7 @@ corr2d_status enqueue_sequential(corr2d_plan_s* p, const void* y_base, void* phi
         ts.count = 1;
         ts.blocks0 = table_blocks(I.g);
         hipError_t e = launch_tables(ts, ts.blocks0, I.g.m, s);
+        if (e == hipSuccess && needs_qn(p)) e = launch_tables_qn(ts, qn_blocks(I.g.m), I.g.m, s);
         if (e != hipSuccess) return device_fail(e, "tables launch");
         PrepSrcInline ps{};
         ps.j[0] = make_prep_job(p, I.g, I.s, (const char*)y_base + I.it.in_offset * isz, I.it.ld_in,

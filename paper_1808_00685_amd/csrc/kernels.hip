@@ -253,9 +253,91 @@ __global__ __launch_bounds__(256) void tables_kernel(Src src) {
     const int64_t total = (int64_t)T.rows_pad * T.kt;
     if (e >= total) return;
     const int64_t r = e / T.kt, j = e % T.kt;
+    // the rows of Q N (Fourier basis, Noda's kernel) come from tables_qn_kernel
+    if (T.basis == B_FOURIER && T.hilbert == H_NODA && r >= T.kp && r < T.kp + T.m && j < T.m) return;
     const double v = table_entry(T, tw, hh, r, j);
     if (T.f64) ((double*)T.table)[e] = v;
     else ((float*)T.table)[e] = (float)v;
+}
+
+// Rows of Q N (Fourier basis, Noda's kernel) in O(m) per frequency.  With
+// theta = 2 pi p / m and d = j - l, a cosine row of Q gives
+//   sum_{l != j} cos(theta l) / (pi (j - l))
+//     = cos(theta j) (Pc(j) - Pc(m-1-j)) + sin(theta j) (Ps(j) + Ps(m-1-j)),
+// Pc(t) = sum_{d=1..t} cos(theta d)/(pi d), Ps likewise with sin (the
+// negative d of the sum fold onto positive ones by parity), and a sine row
+//   sin(theta j) (Pc(j) - Pc(m-1-j)) - cos(theta j) (Ps(j) + Ps(m-1-j)).
+// Workgroup lb handles frequency p = lb: the DC row (p = 0), the pair of
+// rows 2p-1, 2p, or the Nyquist row of an even m (p = m/2); the prefix sums
+// (FP64) are scanned in LDS, 16 m bytes.
+template <class Src>
+__global__ __launch_bounds__(256) void tables_qn_kernel(Src src) {
+    extern __shared__ double pre[];
+    __shared__ double part_c[256], part_s[256];
+    int p;
+    const TableJob T = src.get_q(blockIdx.x, p);
+    if (!(T.basis == B_FOURIER && T.hilbert == H_NODA)) return;
+    const int64_t m = T.m;
+    double* pc = pre;
+    double* ps = pre + m;
+    const int tid = threadIdx.x;
+    const int64_t per = (m + 255) / 256;
+    const int64_t t0 = (int64_t)tid * per, t1 = t0 + per < m ? t0 + per : m;
+    double sc = 0.0, ss = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        if (t > 0) {
+            double sv, cv;
+            sincospi(2.0 * (double)(((int64_t)p * t) % m) / (double)m, &sv, &cv);
+            const double w = 1.0 / (M_PI * (double)t);
+            sc += cv * w;
+            ss += sv * w;
+        }
+        pc[t] = sc;
+        ps[t] = ss;
+    }
+    part_c[tid] = sc;
+    part_s[tid] = ss;
+    __syncthreads();
+    if (tid == 0) {
+        double oc = 0.0, os = 0.0;
+        for (int q = 0; q < 256; ++q) {
+            const double c = part_c[q], s = part_s[q];
+            part_c[q] = oc;
+            part_s[q] = os;
+            oc += c;
+            os += s;
+        }
+    }
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+        pc[t] += part_c[tid];
+        ps[t] += part_s[tid];
+    }
+    __syncthreads();
+    const bool nyq = (m & 1) == 0 && p == m / 2;
+    for (int64_t j = tid; j < m; j += 256) {
+        const double cs = pc[j] - pc[m - 1 - j], sn = ps[j] + ps[m - 1 - j];
+        double sv, cv;
+        sincospi(2.0 * (double)(((int64_t)p * j) % m) / (double)m, &sv, &cv);
+        if (p == 0 || nyq) {
+            const int64_t k = p == 0 ? 0 : m - 1;
+            const double v = cv * cs + sv * sn;
+            const int64_t e = (T.kp + k) * T.kt + j;
+            if (T.f64) ((double*)T.table)[e] = v;
+            else ((float*)T.table)[e] = (float)v;
+        } else {
+            const double vc = M_SQRT2 * (cv * cs + sv * sn);
+            const double vs = -M_SQRT2 * (sv * cs - cv * sn);
+            const int64_t e1 = (T.kp + 2 * p - 1) * T.kt + j, e2 = (T.kp + 2 * p) * T.kt + j;
+            if (T.f64) {
+                ((double*)T.table)[e1] = vc;
+                ((double*)T.table)[e2] = vs;
+            } else {
+                ((float*)T.table)[e1] = (float)vc;
+                ((float*)T.table)[e2] = (float)vs;
+            }
+        }
+    }
 }
 
 // =========================================================================
@@ -1337,6 +1419,14 @@ __global__ __launch_bounds__(256) void interp_kernel(InterpJob J) {
 // =========================================================================
 // Host launchers
 // =========================================================================
+hipError_t launch_tables_qn(const TableSrcInline& src, int blocks, int64_t max_m, hipStream_t s) {
+    hipLaunchKernelGGL(tables_qn_kernel<TableSrcInline>, dim3(blocks), dim3(256), (size_t)(16 * max_m), s, src);
+    return hipGetLastError();
+}
+hipError_t launch_tables_qn(const TableSrcArray& src, int blocks, int64_t max_m, hipStream_t s) {
+    hipLaunchKernelGGL(tables_qn_kernel<TableSrcArray>, dim3(blocks), dim3(256), (size_t)(16 * max_m), s, src);
+    return hipGetLastError();
+}
 hipError_t launch_interp(const InterpJob& J, hipStream_t s) {
     const dim3 grid((unsigned)((J.n + 63) / 64), (unsigned)((J.N + kInterpRows - 1) / kInterpRows));
     hipLaunchKernelGGL(interp_kernel, grid, dim3(256), 0, s, J);

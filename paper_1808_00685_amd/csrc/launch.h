@@ -21,6 +21,9 @@ struct TableSrcInline {
         lb = b - blocks0;
         return j[1];
     }
+    // workgroup b of the Q N kernel (one job: the single and hetero plans
+    // share one table)
+    __device__ TableJob get_q(int b, int& lb) const { lb = b; return j[0]; }
 };
 
 // Jobs in device memory; start[q] is the first block of job q (count + 1
@@ -28,18 +31,28 @@ struct TableSrcInline {
 struct TableSrcArray {
     const TableJob* jobs;
     const int32_t* start;
+    const int32_t* qstart;  // first Q N workgroup of job q (count + 1 entries)
     int32_t count;
     int32_t ncounters;  // ticket counters of the persistent launches (one per tile shape)
     int* counter;       // set to 0 by block 0
-    __device__ TableJob get(int b, int& lb) const {
+    __device__ static int find(const int32_t* st, int count, int b) {
         int lo = 0, hi = count - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (start[mid] <= b) lo = mid;
+            if (st[mid] <= b) lo = mid;
             else hi = mid - 1;
         }
-        lb = b - start[lo];
-        return jobs[lo];
+        return lo;
+    }
+    __device__ TableJob get(int b, int& lb) const {
+        const int q = find(start, count, b);
+        lb = b - start[q];
+        return jobs[q];
+    }
+    __device__ TableJob get_q(int b, int& lb) const {
+        const int q = find(qstart, count, b);
+        lb = b - qstart[q];
+        return jobs[q];
     }
 };
 
@@ -85,5 +98,9 @@ hipError_t launch_corr_persistent(int prec, int fm, int fn, bool out_f64, const 
 int corr_variant_supported(int prec, int fm, int fn);
 int persistent_blocks_per_cu(int prec, int fm, int fn, bool out_f64);
 hipError_t launch_interp(const InterpJob& J, hipStream_t s);
+hipError_t launch_tables_qn(const TableSrcInline& src, int blocks, int64_t max_m, hipStream_t s);
+hipError_t launch_tables_qn(const TableSrcArray& src, int blocks, int64_t max_m, hipStream_t s);
+// Workgroups of the Q N kernel for one table: one per frequency 0..floor(m/2).
+inline int qn_blocks(int64_t m) { return (int)(m / 2 + 1); }
 
 }  // namespace corr2d

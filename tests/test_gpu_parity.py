@@ -369,3 +369,32 @@ def test_interpolation_hetero_f32_input_scaled(gpu):
     phi, psi, _, _ = B.hetero(y1, y2, prec="f64", interp="spline", t_in=t, m_out=m_out, alpha=0.5)
     assert rel_fro(_np(phi), phi_o) <= 1e-12
     assert rel_fro(_np(psi), psi_o) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# Edge sizes: long perturbation axes (centring without the register cache,
+# the largest m), and a very wide heterocorrelation
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "fp8_e4m3"])
+@pytest.mark.parametrize("m,n", [(300, 190), (1000, 70), (4096, 33)])
+def test_long_perturbation_axis(gpu, prec, m, n):
+    S = _rand(m, n, 500 + m)
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, _ = _homo(S, gpu, prec=prec)
+    check_homo_structure(phi, psi)
+    assert rel_fro(phi, phi_o) <= TOL[prec]
+    assert rel_fro(psi, psi_o) <= TOL[prec]
+
+
+def test_wide_heterocorrelation(gpu):
+    m, n1, n2 = 6, 120000, 37
+    S1, S2 = _rand(m, n1, 510), _rand(m, n2, 511)
+    rng = np.random.default_rng(512)
+    i, j = rng.integers(0, n1, 4000), rng.integers(0, n2, 4000)
+    i[:3] = [n1 - 1, 0, n1 - 1]
+    j[:3] = [n2 - 1, n2 - 1, 0]
+    po, qo = oracle.corr2d_entries(S1, i, j, S2=S2)
+    phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), prec="f32")
+    gp, gq = _np(phi), _np(psi)
+    assert rel_fro(gp[i, j], po) <= TOL["f32"]
+    assert rel_fro(gq[i, j], qo) <= TOL["f32"]
