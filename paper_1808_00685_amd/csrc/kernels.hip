@@ -1055,9 +1055,10 @@ __device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds) {
 // contraction runs over K blocks of 16.  Each block's operand rows (left A
 // rows of tile I, right A and B rows of tile J, hi and lo planes for the
 // split form) are 4 KB runs of the K-blocked layout, copied straight into
-// LDS with global_load_lds_dwordx4 (no register staging) through a 3-stage
-// ring: the copies of blocks kb+1 and kb+2 are in flight while block kb
-// feeds the MFMAs.  Each wave waits only for its own copies of block kb
+// LDS with global_load_lds_dwordx4 (no register staging) through a ring of
+// S stages: the copies of blocks kb+2 .. kb+S are in flight while the
+// fragments of block kb+1 are read and those of block kb feed the MFMAs.
+// Each wave waits only for its own copies of the block it reads next
 // (vmcnt) and a bare s_barrier publishes them; a full __syncthreads would
 // also drain the prefetches.
 // ---------------------------------------------------------------------------
@@ -1253,15 +1254,19 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
         }
     };
     // Stage kb+1 always exists where this runs (the number of K blocks is
-    // even), so the fragment reads are unconditional and the compiler waits
-    // for them only before the next step's MFMAs.
+    // even), so the fragment reads are unconditional.
     // The next stage's reads go between the two halves of the MFMAs: the
     // wait for this stage's fragments comes before the first half, and the
     // second half (and the next barrier) hide the new reads' latency.
+    // Each wave finishes its own fragment reads of stage kb (lgkmcnt) before
+    // the barrier, so after it the slot of stage kb is free and the copy of
+    // stage kb + S goes there: every slot of the ring holds a stage in
+    // flight or being read, and a copy has S - 1 steps to land.
     auto step = [&](Frags& Fc, Frags& Fn, int kb) {
-        wait_stages<OPSW, S - 3>(min(S - 3, nkb - 2 - kb));
+        wait_stages<OPSW, S - 2>(min(S - 2, nkb - 2 - kb));
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         lds_barrier();
-        if (kb + S - 1 < nkb) issue(kb + S - 1);
+        if (kb + S < nkb) issue(kb + S);
         mfma_rows(Fc, 0);
         __builtin_amdgcn_sched_barrier(0);
         load_frags(Fn, kb + 1);
@@ -1271,9 +1276,9 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
 
     lds_barrier();   // the ring is free (previous tile of a persistent loop)
 #pragma unroll
-    for (int st = 0; st < S - 1; ++st)
+    for (int st = 0; st < S; ++st)
         if (st < nkb) issue(st);
-    wait_stages<OPSW, S - 2>(min(S - 2, nkb - 1));
+    wait_stages<OPSW, S - 1>(min(S - 1, nkb - 1));
     lds_barrier();
     Frags F0, F1;
     load_frags(F0, 0);
