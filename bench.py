@@ -49,6 +49,10 @@ def rel_fro(g, o):
     return float(np.linalg.norm(g - o) / np.linalg.norm(o))
 
 
+LAYOUT_TEXT = {"upper_aligned": "rows aligned to 128 bytes",
+               "upper_packed": "packed rows"}
+
+
 def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracle_vals,
                 layout="upper_packed", alpha=0.0):
     """Time `steps` calls; returns a dict of measurements for this form."""
@@ -56,7 +60,7 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     plan = B.Plan(m=m, n1=n, n2=0, prec=prec, basis=basis, out_layout=layout,
                   in_dtype="f64", out_dtype=out_dtype, scale_alpha=alpha)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
-    numel = n * (n + 1) // 2
+    numel = B.out_elements(layout, n)
     phi = torch.empty(numel, dtype=tdt, device=y.device)
     psi = torch.empty(numel, dtype=tdt, device=y.device)
     ws = plan.workspace(y.device)
@@ -75,7 +79,10 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     kms = [ev.elapsed_ms(evs[2 * s], evs[2 * s + 1]) for s in range(steps)]
     ev.destroy(evs)
     i, j = sample
-    idx = torch.as_tensor(i * n - (i * (i - 1)) // 2 + (j - i), device=y.device)
+    if layout == "upper_packed":
+        idx = torch.as_tensor(i * n - (i * (i - 1)) // 2 + (j - i), device=y.device)
+    else:
+        idx = torch.as_tensor(B.upper_aligned_index(i, j, n), device=y.device)
     g_phi = phi[idx].double().cpu().numpy()
     g_psi = psi[idx].double().cpu().numpy()
     info = plan.info
@@ -89,7 +96,7 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     planes = {"f64": 8, "f32": 4, "split_bf16": 4, "bf16": 2, "f16": 2, "fp8_e4m3": 1}[prec]
     kernel_bytes = 2 * entries * esz + 2 * n * info.k_pad * planes
     res = {
-        "prec": prec, "basis": basis, "scale_alpha": alpha,
+        "prec": prec, "basis": basis, "scale_alpha": alpha, "layout": layout,
         "ms_per_step": wall * 1e3 / steps,
         "entries_per_s": entries / (wall / steps),
         "kernel_ms": kernel_ms,
@@ -317,6 +324,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--m", type=int, default=256)
     ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--layout", default="upper_aligned", choices=["upper_aligned", "upper_packed"],
+                    help="storage of the upper triangle in the headline line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -342,19 +351,24 @@ def main():
     y = torch.as_tensor(S, device=dev)
     ev = HipEvents()
 
+    layout = args.layout
     main_res = run_variant(B, torch, y, n, m, "split_bf16", "fourier", args.steps, args.warmup,
-                           ev, sample, oracle_vals)
+                           ev, sample, oracle_vals, layout=layout)
     variants = []
     if not args.no_variants:
         vs = args.variant_steps
+        # the headline form in the other upper-triangle layout
+        other = "upper_packed" if layout == "upper_aligned" else "upper_aligned"
+        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, sample,
+                                    oracle_vals, layout=other))
         for prec, basis in (("f32", "fourier"), ("bf16", "fourier"), ("bf16", "time"),
                             ("f64", "fourier")):
             variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, sample,
-                                        oracle_vals))
+                                        oracle_vals, layout=layout))
         # Pareto scaling (alpha = 0.5) of the headline form
         pareto_vals = oracle.corr2d_entries(S, sample[0], sample[1], alpha=0.5)
         variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, sample,
-                                    pareto_vals, alpha=0.5))
+                                    pareto_vals, alpha=0.5, layout=layout))
 
     workloads = []
     if not args.no_workloads:
@@ -380,9 +394,9 @@ def main():
         "vs_baseline": None,
         "dtype": "split-bf16",
         "data": "synthetic",
-        "config": {"workload": f"homocorrelation m={m} n={n} band spectra, upper triangle, "
-                               "FP32 output, Fourier basis, Noda kernel",
-                   "m": m, "n": n, "layout": "upper_packed", "prec": "split_bf16",
+        "config": {"workload": f"homocorrelation m={m} n={n} band spectra, upper triangle "
+                               f"({LAYOUT_TEXT[layout]}), FP32 output, Fourier basis, Noda kernel",
+                   "m": m, "n": n, "layout": layout, "prec": "split_bf16",
                    "entries_per_step": n * (n + 1) // 2},
         "roofline": {
             "bound": "mfma", "kernel": f"corr2_kernel<split_bf16> ({main_res['tile']} tiles)",

@@ -39,6 +39,14 @@
  * contiguous, the paper's input matrix of Sec. 3).  Full outputs are
  * row-major n1 x ld_out.  UPPER_PACKED (homocorrelation only) stores row i's
  * entries j = i..n-1 contiguously at offset i*n - i*(i-1)/2 + (j - i).
+ * UPPER_ALIGNED (homocorrelation only) stores the same entries with every row
+ * starting on a 32-element boundary (128 bytes of FP32): row i covers the
+ * columns c(i) = 32*floor(i/32) .. N32-1, N32 = n rounded up to a multiple of
+ * 32, so element (i, j), j >= i, sits at corr2d_upper_aligned_index(i, j, n)
+ * below.  The slots of columns c(i)..i-1 and n..N32-1 are padding that the
+ * library never writes; one plane holds corr2d_upper_aligned_elements(n)
+ * elements (n (n+1)/2 plus at most 62 n).  Stores of whole cache lines make
+ * this layout faster to write than UPPER_PACKED, whose rows start mid-line.
  * A plan owns host memory only and can be created without a GPU.
  *
  * Calls are asynchronous on the given HIP stream (a hipStream_t passed as
@@ -95,7 +103,23 @@ typedef enum corr2d_hilbert {
                                      bin for even m); Fourier basis only            */
 } corr2d_hilbert;
 typedef enum corr2d_norm { CORR2D_NORM_NODA = 0, CORR2D_NORM_PAPER = 1, CORR2D_NORM_CUSTOM = 2 } corr2d_norm;
-typedef enum corr2d_layout { CORR2D_LAYOUT_FULL = 0, CORR2D_LAYOUT_UPPER_PACKED = 1 } corr2d_layout;
+typedef enum corr2d_layout {
+    CORR2D_LAYOUT_FULL = 0,
+    CORR2D_LAYOUT_UPPER_PACKED = 1,
+    CORR2D_LAYOUT_UPPER_ALIGNED = 2
+} corr2d_layout;
+
+/* Offset of element (i, j), 0 <= i <= j < n, in the UPPER_ALIGNED layout:
+ * with i = 32 q + r, row i starts at i*N32 - 32 (16 q (q-1) + r q), the sum
+ * of the lengths N32 - 32 floor(k/32) of the rows k < i.                    */
+static inline int64_t corr2d_upper_aligned_index(int64_t i, int64_t j, int64_t n) {
+    const int64_t n32 = (n + 31) / 32 * 32, q = i / 32, r = i % 32;
+    return i * n32 - 32 * (16 * q * (q - 1) + r * q) + (j - 32 * q);
+}
+/* Elements of one UPPER_ALIGNED output plane of an n x n correlation.      */
+static inline int64_t corr2d_upper_aligned_elements(int64_t n) {
+    return corr2d_upper_aligned_index(n, 32 * (n / 32), n);
+}
 typedef enum corr2d_dtype { CORR2D_DTYPE_F64 = 0, CORR2D_DTYPE_F32 = 1 } corr2d_dtype;
 
 /* desc.flags */
@@ -188,8 +212,8 @@ void corr2d_desc_init(corr2d_desc* d);
 
 /* Validate d and build a plan in host memory.  No device call is made.
  * EINVAL: m < 2, n1 < 1, n2 < 0, a stride smaller than its row, an unknown
- * enum value, CUSTOM norm with a non-finite norm_value, UPPER_PACKED for a
- * heterocorrelation.  EUNSUPPORTED: FP8 with per-band scaling forced off.   */
+ * enum value, CUSTOM norm with a non-finite norm_value, UPPER_PACKED or
+ * UPPER_ALIGNED for a heterocorrelation.  EUNSUPPORTED: FP8 with per-band scaling forced off.   */
 corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d);
 
 /* Batched homocorrelation of count independent data sets (count >= 1); the

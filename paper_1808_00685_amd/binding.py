@@ -21,7 +21,8 @@ BASIS = {"fourier": 0, "time": 1}
 HILBERT = {"noda": 0, "circular": 1, "r_compat": 2}
 INTERP = {"none": 0, "linear": 1, "spline": 2}
 NORM = {"noda": 0, "paper": 1, "custom": 2}
-LAYOUT = {"full": 0, "upper_packed": 1}
+LAYOUT = {"full": 0, "upper_packed": 1, "upper_aligned": 2}
+LAYOUT_NAMES = {v: k for k, v in LAYOUT.items()}
 DTYPE = {"f64": 0, "f32": 1}
 FLAG_PER_BAND_SCALE = 0x1
 FLAG_NO_PER_BAND_SCALE = 0x2
@@ -275,6 +276,31 @@ class Plan:
             self.handle = None
 
 
+def upper_aligned_index(i, j, n):
+    """Offset of element (i, j), i <= j < n, in the UPPER_ALIGNED layout
+    (corr2d_upper_aligned_index of the C header); works on numpy arrays."""
+    import numpy as np
+    i = np.asarray(i, dtype=np.int64)
+    j = np.asarray(j, dtype=np.int64)
+    n32 = (int(n) + 31) // 32 * 32
+    q, r = i // 32, i % 32
+    return i * n32 - 32 * (16 * q * (q - 1) + r * q) + (j - 32 * q)
+
+
+def upper_aligned_elements(n):
+    """Elements of one UPPER_ALIGNED output plane (corr2d_upper_aligned_elements)."""
+    return int(upper_aligned_index(n, 32 * (n // 32), n))
+
+
+def out_elements(layout, n1, n2=0):
+    """Elements of one output plane of an n1 x n1 (or n1 x n2) correlation."""
+    if layout == "upper_packed":
+        return n1 * (n1 + 1) // 2
+    if layout == "upper_aligned":
+        return upper_aligned_elements(n1)
+    return n1 * (n2 or n1)
+
+
 def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="fourier",
          hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0,
          t_in=None, interp="none", m_out=None, stream=None):
@@ -293,7 +319,7 @@ def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="f
                 norm_value=norm_value, out_layout=layout, flags=flags, tile=tile,
                 scale_alpha=alpha, t_in=t_in, interp=interp)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
-    numel = n * (n + 1) // 2 if layout == "upper_packed" else n * n
+    numel = out_elements(layout, n)
     phi = torch.empty(numel, dtype=tdt, device=y.device)
     psi = torch.empty(numel, dtype=tdt, device=y.device)
     ws = plan.workspace(y.device)

@@ -193,7 +193,7 @@ corr2d_status check_common(const corr2d_desc* d) {
     if (d->hilbert == CORR2D_HILBERT_R_COMPAT && d->basis != CORR2D_BASIS_FOURIER)
         return fail(CORR2D_EUNSUPPORTED, "the R-compatible bin list needs the Fourier basis");
     if (!valid_enum(d->norm_mode, 0, 2)) return fail(CORR2D_EINVAL, "unknown norm_mode %d", d->norm_mode);
-    if (!valid_enum(d->out_layout, 0, 1)) return fail(CORR2D_EINVAL, "unknown out_layout %d", d->out_layout);
+    if (!valid_enum(d->out_layout, 0, 2)) return fail(CORR2D_EINVAL, "unknown out_layout %d", d->out_layout);
     if (d->norm_mode == CORR2D_NORM_CUSTOM && !std::isfinite(d->norm_value))
         return fail(CORR2D_EINVAL, "CUSTOM norm needs a finite norm_value");
     if (!std::isfinite(d->scale_alpha))
@@ -439,8 +439,8 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     if (d->n1 < 1 || d->n1 > kMaxN) return fail(CORR2D_EINVAL, "n1 = %lld out of range", (long long)d->n1);
     if (d->n2 < 0 || d->n2 > kMaxN) return fail(CORR2D_EINVAL, "n2 = %lld out of range", (long long)d->n2);
     const bool hetero = d->n2 > 0;
-    if (hetero && d->out_layout == CORR2D_LAYOUT_UPPER_PACKED)
-        return fail(CORR2D_EINVAL, "UPPER_PACKED output is defined for homocorrelation only");
+    if (hetero && d->out_layout != CORR2D_LAYOUT_FULL)
+        return fail(CORR2D_EINVAL, "upper-triangle outputs are defined for homocorrelation only");
     const int64_t ld1 = d->ld_in1 ? d->ld_in1 : d->n1;
     const int64_t ld2 = d->ld_in2 ? d->ld_in2 : d->n2;
     if (ld1 < d->n1) return fail(CORR2D_EINVAL, "ld_in1 < n1");
@@ -553,7 +553,10 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
         }
         I.ntiles = triangle_tiles(I.g.n_pad / (32 * I.tile.fm), I.tile.fm / I.tile.fn);
         const int64_t outn = common->out_layout == CORR2D_LAYOUT_UPPER_PACKED
-                                 ? I.it.n * (I.it.n + 1) / 2 : I.it.n * I.it.n;
+                                 ? I.it.n * (I.it.n + 1) / 2
+                             : common->out_layout == CORR2D_LAYOUT_UPPER_ALIGNED
+                                 ? corr2d_upper_aligned_elements(I.it.n)
+                                 : I.it.n * I.it.n;
         p->out_elements = std::max(p->out_elements, I.it.out_offset + outn);
     }
     // grouped by tile shape, each group in descending cost order (longest

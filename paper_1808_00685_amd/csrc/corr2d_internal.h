@@ -8,7 +8,7 @@ namespace corr2d {
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_SPLIT = 2, P_BF16 = 3, P_F16 = 4, P_FP8 = 5 };
 enum Basis : int { B_FOURIER = 0, B_TIME = 1 };
 enum Hilbert : int { H_NODA = 0, H_CIRCULAR = 1, H_R_COMPAT = 2 };
-enum Layout : int { L_FULL = 0, L_UPPER = 1 };
+enum Layout : int { L_FULL = 0, L_UPPER = 1, L_UPPER_ALIGNED = 2 };
 
 // 16-bit formats use the LDS-staged contraction kernel and the K-blocked
 // operand layout (see blocked_index); the others the register-direct kernel

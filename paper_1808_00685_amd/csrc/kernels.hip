@@ -30,6 +30,7 @@
 
 #include "corr2d_internal.h"
 #include "launch.h"
+#include "tile_order.h"
 
 namespace corr2d {
 
@@ -87,46 +88,6 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
     const int64_t per = nb / 8, rem = nb % 8;
     const int64_t x = b % 8, s = b / 8;
     return x * per + (x < rem ? x : rem) + s;
-}
-
-// Upper-triangle tile order for tiles R times as tall as they are wide
-// (row tile I covers rows [I*R*w, (I+1)*R*w) for column tiles of width w, so
-// tile (I, J) holds an element with j >= i exactly when J >= R*I).  Tiles
-// are grouped by G column tiles: group g covers column tiles [gG, gG+G);
-// inside it the row tiles follow one another, each taking the columns of the
-// group that lie on or above the diagonal.  Tiles that run together share a
-// few row panels and one group of column panels.
-__host__ __device__ inline void decode_upper(int64_t t, int TI, int TJ, int R, int G, int& I, int& J) {
-    int c0 = 0, c1 = 0, nfull = 0;
-    for (c0 = 0;; c0 += G) {
-        c1 = c0 + G < TJ ? c0 + G : TJ;
-        nfull = c0 / R + 1 < TI ? c0 / R + 1 : TI;   // rows whose diagonal lies left of the group
-        int64_t cnt = (int64_t)nfull * (c1 - c0);
-        for (int r = nfull; r < TI && R * r < c1; ++r) cnt += c1 - R * r;
-        if (t < cnt) break;
-        t -= cnt;
-    }
-    const int gw = c1 - c0;
-    if (t < (int64_t)nfull * gw) {
-        I = (int)(t / gw);
-        J = c0 + (int)(t % gw);
-        return;
-    }
-    t -= (int64_t)nfull * gw;
-    int r = nfull;
-    while (t >= c1 - R * r) { t -= c1 - R * r; ++r; }
-    I = r;
-    J = R * r + (int)t;
-}
-
-// Full-grid tile order for heterocorrelation, grouped by G column tiles.
-__device__ inline void decode_full(int64_t t, int Ti, int Tj, int G, int& I, int& J) {
-    const int64_t per_group = (int64_t)Ti * G;
-    const int g = (int)(t / per_group);
-    const int64_t r = t - (int64_t)g * per_group;
-    const int gw = min(G, Tj - g * G);
-    I = (int)(r / gw);
-    J = g * G + (int)(r % gw);
 }
 
 // =========================================================================
@@ -741,64 +702,40 @@ __device__ inline void mma(typename Frag<P>::Acc& acc, const typename Frag<P>::T
     }
 }
 
-__device__ inline void store_val(void* base, int64_t idx, double v, int f64) {
-    if (f64) __builtin_nontemporal_store(v, (double*)base + idx);
-    else __builtin_nontemporal_store((float)v, (float*)base + idx);
-}
-
-__device__ inline int64_t packed_index(int64_t i, int64_t j, int64_t n) {
-    return i * n - (i * (i - 1)) / 2 + (j - i);
-}
+// Row starts of the upper-triangle layouts.  Row indices and n are below
+// 2^24 (the plan's limit), so 32 x 32 -> 64-bit products suffice.
+__device__ inline int64_t mul64(uint32_t a, uint32_t b) { return (int64_t)((uint64_t)a * b); }
 // Start of packed row i minus i, so that element (i, j) is at base + j.
 __device__ inline int64_t packed_row_base(int64_t i, int64_t n) {
-    return i * n - (i * (i - 1)) / 2 - i;
+    const uint32_t ii = (uint32_t)i;
+    return mul64(ii, (uint32_t)n) - (mul64(ii, ii - 1u) >> 1) - i;
+}
+// Row-aligned upper layout: row i starts at i N32 - 32 (16 q (q-1) + r q),
+// i = 32 q + r, and holds the columns from 32 q on; the start minus 32 q, so
+// that element (i, j) is at base + j.  Every row starts on a multiple of 32
+// elements.
+__device__ inline int64_t aligned_row_base(int64_t i, int64_t n) {
+    const uint32_t ii = (uint32_t)i, q = ii >> 5, r = ii & 31u;
+    const uint32_t n32 = ((uint32_t)n + 31u) & ~31u;
+    return mul64(ii, n32) - 32 * (16 * mul64(q, q - 1u) + mul64(r, q)) - 32 * (int64_t)q;
 }
 
-// 1/s for a power-of-two scale s, exactly.
-__device__ inline double inv_pow2(float s) { return ldexp(1.0, -ilogbf(s)); }
-
-// FP64 factors of the epilogue: Phi(i,j) = acc * c / (sL_i sRA_j),
-// Psi(i,j) = acc * c / (sL_i sRB_j).  Scales are powers of two, so the
-// factors are exact and applying them adds no rounding.
-__device__ inline void col_factors(const CorrJob& C, int64_t j, double& fa, double& fb) {
-    if (!C.scaled) {
-        fa = fb = C.c;
-        return;
-    }
-    fa = C.c * inv_pow2(C.sRA[j]);
-    fb = C.c * inv_pow2(C.sRB[j]);
+// s_waitcnt through the builtin, so that the compiler's own wait tracking
+// sees it (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt
+// 11:8; a field at its maximum does not wait).
+template <int VM, int LGKM>
+__device__ inline void waitcnt() {
+    static_assert(VM >= 0 && VM <= 63 && LGKM >= 0 && LGKM <= 15, "waitcnt fields");
+    __builtin_amdgcn_s_waitcnt((VM & 15) | (7 << 4) | (LGKM << 8) | ((VM >> 4) << 14));
 }
-__device__ inline double row_factor(const CorrJob& C, int64_t i) {
-    return C.scaled ? inv_pow2(C.sL[i]) : 1.0;
+template <int N>
+__device__ inline void wait_vmcnt() {
+    waitcnt<N, 15>();
 }
+__device__ inline void wait_lgkm0() { waitcnt<63, 0>(); }
 
-// Epilogue for one element with every check: bounds, zero asynchronous
-// diagonal, exact mirror (FULL) or packed (UPPER) stores for homocorrelation.
-// vphi, vpsi are already normalized.
-__device__ inline void emit(const CorrJob& C, int64_t i, int64_t j, double phi, double psi) {
-    if (i >= C.n1 || j >= C.n2) return;
-    if (!C.homo) {
-        store_val(C.phi, i * C.ld_out + j, phi, C.out_f64);
-        store_val(C.psi, i * C.ld_out + j, psi, C.out_f64);
-        return;
-    }
-    if (i > j) return;
-    if (i == j) psi = 0.0;
-    if (C.layout == L_UPPER) {
-        const int64_t p = packed_index(i, j, C.n1);
-        store_val(C.phi, p, phi, C.out_f64);
-        store_val(C.psi, p, psi, C.out_f64);
-    } else {
-        store_val(C.phi, i * C.ld_out + j, phi, C.out_f64);
-        store_val(C.psi, i * C.ld_out + j, psi, C.out_f64);
-        if (i != j) {
-            store_val(C.phi, j * C.ld_out + i, phi, C.out_f64);
-            store_val(C.psi, j * C.ld_out + i, -psi, C.out_f64);
-        }
-    }
-}
-
-// One output tile (I, J) of size (32 FM) x (32 FN) computed by 4 waves (2x2).
+// Workgroup barrier that waits for no memory operation: copies into LDS and
+// global stores stay in flight across it.
 __device__ inline void lds_barrier() {
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
@@ -807,7 +744,7 @@ __device__ inline void lds_barrier() {
 // Barrier after this wave's own LDS writes (ds_write is asynchronous): wait
 // for them (lgkmcnt), but not for outstanding global stores (vmcnt).
 __device__ inline void lds_write_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    wait_lgkm0();
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
 }
@@ -837,59 +774,109 @@ __device__ inline V4<float> row_unscale(V4<float> v, int e) {
     return V4<float>{ldexpf(v.x, e), ldexpf(v.y, e), ldexpf(v.z, e), ldexpf(v.w, e)};
 }
 
+// Four consecutive outputs with 16-byte vector stores whatever the address's
+// alignment (the packed layout's rows start anywhere): the vector types
+// below promise only element alignment, and global stores accept that.
+typedef float f4_ua __attribute__((ext_vector_type(4), aligned(4)));
+typedef double d2_ua __attribute__((ext_vector_type(2), aligned(8)));
 template <class OT>
-__device__ inline void put4(void* base, int64_t idx, V4<OT> v, bool f64, bool aligned) {
-    if (f64) {
-        double* d = (double*)base + idx;
-        if (aligned) {
-            *(double2*)d = make_double2(v.x, v.y);
-            *(double2*)(d + 2) = make_double2(v.z, v.w);
-        } else {
-            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-        }
+__device__ inline void put4(OT* o, int64_t idx, V4<OT> v) {
+    OT* d = o + idx;
+    if constexpr (std::is_same<OT, double>::value) {
+        *(d2_ua*)d = d2_ua{v.x, v.y};
+        *(d2_ua*)(d + 2) = d2_ua{v.z, v.w};
     } else {
-        float* f = (float*)base + idx;
-        if (aligned) *(float4*)f = make_float4(v.x, v.y, v.z, v.w);
-        else { f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w; }
+        *(f4_ua*)d = f4_ua{v.x, v.y, v.z, v.w};
     }
 }
-template <class OT>
-__device__ inline void put1(void* base, int64_t idx, OT v, bool f64) {
-    if (f64) ((double*)base)[idx] = v;
-    else ((float*)base)[idx] = (float)v;
-}
 
+// Exponents that undo the power-of-two operand scales of one TM x TN output
+// tile, gathered once per tile into an LDS table for the epilogue:
+// [0, TM) the left rows i0 + r, [TM, TM + TN) the right A columns j0 + c,
+// [TM + TN, TM + 2 TN) the right B columns (0 without per-band scaling and
+// past the last row or column).  NT threads share the loads.  Reading the
+// scales in the epilogue itself would put a load between stores, and the wait
+// for it would also wait for every store before it (vmcnt counts both).
+template <int TM, int TN, int NT>
+struct ScaleExps {
+    static constexpr int N = TM + 2 * TN;
+    static constexpr int PER = (N + NT - 1) / NT;
+    float v[PER];   // the scales themselves
+    bool ok[PER];   // entry exists and is scaled
+    // Branch-free loads (entries past the data read sL[0] and are dropped):
+    // their values are first used in store(), so the wait for them comes
+    // there and the work in between hides it.
+    __device__ void load(const CorrJob& C, int64_t i0, int64_t j0, int tid) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + k * NT;
+            const bool row = e < TM, b = e >= TM + TN;
+            const int64_t j = j0 + e - TM - (b ? TN : 0);
+            ok[k] = C.scaled && e < N && (row ? i0 + e < C.n1 : j < C.n2);
+            v[k] = 1.0f;
+        }
+        if (C.scaled) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int e = tid + k * NT;
+                const bool row = e < TM, b = e >= TM + TN;
+                const int64_t j = j0 + e - TM - (b ? TN : 0);
+                const float* src = row ? C.sL + i0 + e : (b ? C.sRB : C.sRA) + j;
+                v[k] = *(ok[k] ? src : C.sL);
+            }
+        }
+    }
+    // write the table; the caller's next barrier publishes it
+    __device__ void store(int* t, int tid) const {
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if (tid + k * NT < N) t[tid + k * NT] = ok[k] ? -pow2_exp(v[k]) : 0;
+        wait_lgkm0();
+    }
+};
+
+// Store one (TM x TN) output tile held in LDS in the output type OT, rows
+// of TN + 4 elements, already scaled by c / sR_j; rexp[r] (LDS) is the
+// exponent of tile row r's scale (0 when unscaled), applied exactly with
+// ldexp.  NT threads.  Tiles wholly inside the output and off the diagonal
+// (nearly all) take a straight-line path: no per-element checks and no
+// branch between passes, so the passes' LDS reads and stores interleave.
+// Nothing here reads global memory: a load between the stores would make
+// each pass wait for every earlier store (vmcnt counts both).
 template <int TM, int TN, int NT, class OT>
-__device__ inline void store_tile(const CorrJob& C, int64_t i0, int64_t j0, const OT* T, bool psi, int tid) {
+__device__ inline void store_tile(const CorrJob& C, int64_t i0, int64_t j0, const OT* T, const int* rexp,
+                                  bool psi, int tid) {
     constexpr int P = TN + 4;             // row pitch in elements
     constexpr int RPP = NT / (TN / 4);    // rows per pass of the direct stores
     static_assert(TM % RPP == 0, "direct-store passes");
     const bool homo = C.homo;
     const bool diag = homo && j0 <= i0 + TM - 1;   // tile reaches the diagonal
-    void* out = psi ? C.psi : C.phi;
-    const bool f64 = C.out_f64;
-    const bool inside = i0 + TM <= C.n1 && j0 + TN <= C.n2;
+    OT* out = (OT*)(psi ? C.psi : C.phi);
+    const bool fast = i0 + TM <= C.n1 && j0 + TN <= C.n2 && !diag;
     const int cl = (tid % (TN / 4)) * 4;  // 4 consecutive columns per thread
     const int rsub = tid / (TN / 4);
+    auto row = [&](int rl) { return row_unscale(*(const V4<OT>*)(T + rl * P + cl), rexp[rl]); };
     if (!homo || C.layout == L_FULL) {
         // direct rows (homo: the upper part; diagonal tiles mask j < i)
-        for (int pass = 0; pass < TM / RPP; ++pass) {
-            const int rl = pass * RPP + rsub;
-            const int64_t i = i0 + rl, j = j0 + cl;
-            V4<OT> v = *(const V4<OT>*)(T + rl * P + cl);
-            if (C.scaled && i < C.n1) v = row_unscale(v, -pow2_exp(C.sL[i]));
-            const int64_t idx = i * C.ld_out + j;
-            if (inside && !diag) {
-                put4(out, idx, v, f64, ((idx & 3) == 0) && ((C.ld_out & 3) == 0));
-            } else if (i < C.n1) {
-                const OT e[4] = {v.x, v.y, v.z, v.w};
+        if (fast) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t jj = j + q;
-                    if (jj >= C.n2) break;
-                    if (diag && jj < i) continue;
-                    put1(out, idx + q, e[q], f64);
-                }
+            for (int pass = 0; pass < TM / RPP; ++pass) {
+                const int rl = pass * RPP + rsub;
+                put4(out, (i0 + rl) * C.ld_out + j0 + cl, row(rl));
+            }
+        } else {
+#pragma unroll 4
+            for (int pass = 0; pass < TM / RPP; ++pass) {
+                const int rl = pass * RPP + rsub;
+                const int64_t i = i0 + rl, j = j0 + cl;
+                const V4<OT> v = row(rl);
+                const OT e[4] = {v.x, v.y, v.z, v.w};
+                if (i < C.n1)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t jj = j + q;
+                        if (jj < C.n2 && !(diag && jj < i)) out[i * C.ld_out + jj] = e[q];
+                    }
             }
         }
         if (homo) {
@@ -901,52 +888,59 @@ __device__ inline void store_tile(const CorrJob& C, int64_t i0, int64_t j0, cons
             const int rsubm = tid / (TM / 4);
             const OT sg = psi ? OT(-1) : OT(1);
             // rows i0 + cc .. cc+3 of the tile are this thread's mirror columns
-            int er[4] = {0, 0, 0, 0};
-            if (C.scaled)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (i0 + cc + q < C.n1) er[q] = -pow2_exp(C.sL[i0 + cc + q]);
-            for (int pass = 0; pass < TN / MPP; ++pass) {
-                const int rr = pass * MPP + rsubm;
-                const int64_t jm = j0 + rr, im = i0 + cc;
-                V4<OT> t{sg * T[(cc + 0) * P + rr], sg * T[(cc + 1) * P + rr],
-                         sg * T[(cc + 2) * P + rr], sg * T[(cc + 3) * P + rr]};
-                if (C.scaled)
-                    t = V4<OT>{ldexp(t.x, er[0]), ldexp(t.y, er[1]), ldexp(t.z, er[2]), ldexp(t.w, er[3])};
-                const int64_t midx = jm * C.ld_out + im;
-                if (inside && !diag) {
-                    put4(out, midx, t, f64, ((midx & 3) == 0) && ((C.ld_out & 3) == 0));
-                } else if (jm < C.n1) {
+            const int er[4] = {rexp[cc], rexp[cc + 1], rexp[cc + 2], rexp[cc + 3]};
+            auto col = [&](int rr) {
+                return V4<OT>{ldexp(sg * T[(cc + 0) * P + rr], er[0]), ldexp(sg * T[(cc + 1) * P + rr], er[1]),
+                              ldexp(sg * T[(cc + 2) * P + rr], er[2]), ldexp(sg * T[(cc + 3) * P + rr], er[3])};
+            };
+            if (fast) {
+#pragma unroll 8
+                for (int pass = 0; pass < TN / MPP; ++pass) {
+                    const int rr = pass * MPP + rsubm;
+                    put4(out, (j0 + rr) * C.ld_out + i0 + cc, col(rr));
+                }
+            } else {
+#pragma unroll 4
+                for (int pass = 0; pass < TN / MPP; ++pass) {
+                    const int rr = pass * MPP + rsubm;
+                    const int64_t jm = j0 + rr, im = i0 + cc;
+                    const V4<OT> t = col(rr);
                     const OT e[4] = {t.x, t.y, t.z, t.w};
+                    if (jm < C.n1)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int64_t ii = im + q;
-                        if (ii >= C.n1) break;
-                        if (diag && ii >= jm) continue;   // strictly lower part (row jm > col ii)
-                        put1(out, midx + q, e[q], f64);
-                    }
+                        for (int q = 0; q < 4; ++q) {
+                            const int64_t ii = im + q;
+                            // strictly lower part (row jm > col ii)
+                            if (ii < C.n1 && !(diag && ii >= jm)) out[jm * C.ld_out + ii] = e[q];
+                        }
                 }
             }
         }
     } else {
-        // UPPER_PACKED: element (i, j) at rowbase(i) + j, j >= i
-        for (int pass = 0; pass < TM / RPP; ++pass) {
-            const int rl = pass * RPP + rsub;
-            const int64_t i = i0 + rl, j = j0 + cl;
-            if (i >= C.n1) break;
-            V4<OT> v = *(const V4<OT>*)(T + rl * P + cl);
-            if (C.scaled) v = row_unscale(v, -pow2_exp(C.sL[i]));
-            const int64_t idx = packed_row_base(i, C.n1) + j;
-            if (inside && !diag) {
-                put4(out, idx, v, f64, (idx & 3) == 0);
-            } else {
-                const OT e[4] = {v.x, v.y, v.z, v.w};
+        // upper triangle: element (i, j), j >= i, at rowbase(i) + j, packed
+        // (UPPER_PACKED) or with 32-element aligned rows (UPPER_ALIGNED)
+        const bool packed = C.layout == L_UPPER;
+        auto base = [&](int64_t i) { return packed ? packed_row_base(i, C.n1) : aligned_row_base(i, C.n1); };
+        if (fast) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t jj = j + q;
-                    if (jj >= C.n2) break;
-                    if (jj < i) continue;
-                    put1(out, idx + q, e[q], f64);
+            for (int pass = 0; pass < TM / RPP; ++pass) {
+                const int rl = pass * RPP + rsub;
+                put4(out, base(i0 + rl) + j0 + cl, row(rl));
+            }
+        } else {
+#pragma unroll 4
+            for (int pass = 0; pass < TM / RPP; ++pass) {
+                const int rl = pass * RPP + rsub;
+                const int64_t i = i0 + rl, j = j0 + cl;
+                const V4<OT> v = row(rl);
+                const OT e[4] = {v.x, v.y, v.z, v.w};
+                if (i < C.n1) {
+                    const int64_t b = base(i);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t jj = j + q;
+                        if (jj < C.n2 && jj >= i) out[b + jj] = e[q];
+                    }
                 }
             }
         }
@@ -958,8 +952,10 @@ __host__ __device__ constexpr int corr_lds_bytes(int fm, int fn, bool out_f64) {
     return 32 * fm * (32 * fn + 4) * (out_f64 ? 8 : 4);
 }
 
+// One output tile (I, J) of size (32 FM) x (32 FN) computed by 4 waves (2x2)
+// with register-direct fragments, then written through LDS.
 template <int P, int FM, int FN>
-__device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds) {
+__device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds, int* sexp) {
     using FT = typename Frag<P>::T;
     using AT = typename Frag<P>::Acc;
     constexpr int KS = Frag<P>::KS;
@@ -970,6 +966,9 @@ __device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds) {
     const int64_t i0 = (int64_t)I * BM + (wave >> 1) * (16 * FM);
     const int64_t j0 = (int64_t)J * BN + (wave & 1) * (16 * FN);
     const int kofs = kg * (KS / 4);
+    // the scales' exponents, loaded ahead of the K loop (its own waits cover them)
+    ScaleExps<BM, BN, 256> se;
+    se.load(C, (int64_t)I * BM, (int64_t)J * BN, threadIdx.x);
 
     AT ap[FM][FN], aq[FM][FN];
 #pragma unroll
@@ -1017,14 +1016,14 @@ __device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds) {
     asm volatile("" : "+v"(tid));
     const int64_t ti0 = (int64_t)I * BM, tj0 = (int64_t)J * BN;
     const bool diag = C.homo && tj0 <= ti0 + BM - 1;
+    se.store(sexp, tid);
     auto stage = [&](auto* T, AT (&acc)[FM][FN], bool psi) {
         using OT = typename std::remove_pointer<decltype(T)>::type;
         lds_barrier();   // previous readers of the LDS are done
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
             const int jl = (int)(j0 - tj0) + b * 16 + row16;
-            double fc = C.c;
-            if (C.scaled) fc *= inv_pow2(psi ? C.sRB[tj0 + jl] : C.sRA[tj0 + jl]);
+            const double fc = ldexp(C.c, sexp[BM + (psi ? BN : 0) + jl]);
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -1036,7 +1035,7 @@ __device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds) {
                 }
         }
         lds_write_barrier();
-        store_tile<BM, BN, 256, OT>(C, ti0, tj0, T, psi, tid);
+        store_tile<BM, BN, 256, OT>(C, ti0, tj0, T, sexp, psi, tid);
     };
     if (C.out_f64) {
         stage((double*)lds, ap, false);
@@ -1100,10 +1099,7 @@ template <int P, int TM> constexpr int corr2_lds_bytes() {
                : TM * (kTileN2 + 4) * 4;
 }
 
-template <int N>
-__device__ inline void wait_vmcnt() {
-    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
+
 // Wait until at most `ahead` stages of OPSW loads each are outstanding
 // (vector memory operations of one wave complete in issue order).
 template <int OPSW, int MAXA>
@@ -1122,7 +1118,8 @@ __device__ inline void wait_stages(int ahead) {
 // store_tile writes it out.  Accumulator register r of lane l holds row
 // 8(r/4) + 4(l/32) + r%4 and column l%32 of its 32 x 32 block.
 template <int TM>
-__device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][2], char* lds, bool psi) {
+__device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][2], char* lds,
+                                 const int* sexp, bool psi) {
     float* T = (float*)lds;
     // opaque copy of the thread index: keeps the index arithmetic below
     // inside a persistent tile loop instead of hoisted and spilled
@@ -1136,8 +1133,7 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const int jl = wj * 64 + b * 32 + (lane & 31);
-        double fc = C.c;
-        if (C.scaled) fc *= inv_pow2(psi ? C.sRB[j0 + jl] : C.sRA[j0 + jl]);
+        const double fc = ldexp(C.c, sexp[TM + (psi ? kTileN2 : 0) + jl]);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1149,7 +1145,7 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
             }
     }
     lds_write_barrier();
-    store_tile<TM, kTileN2, threads2(TM), float>(C, i0, j0, T, psi, tid);
+    store_tile<TM, kTileN2, threads2(TM), float>(C, i0, j0, T, sexp, psi, tid);
 }
 
 // One TM x 128 output tile: the K loop over a ring of LDS stages filled by
@@ -1158,7 +1154,7 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
 // synchronous right panel and 4 for the asynchronous one; wave w copies
 // chunks w, w + NW, ... of every plane.
 template <int P, int TM>
-__device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
+__device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int* sexp) {
     using FT = typename Wide<P>::T;
     constexpr int PL = planes(P);
     constexpr int S = ring_stages<P, TM>();
@@ -1264,7 +1260,7 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
     // flight or being read, and a copy has S - 1 steps to land.
     auto step = [&](Frags& Fc, Frags& Fn, int kb) {
         wait_stages<OPSW, S - 2>(min(S - 2, nkb - 2 - kb));
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        wait_lgkm0();
         lds_barrier();
         if (kb + S < nkb) issue(kb + S);
         mfma_rows(Fc, 0);
@@ -1290,30 +1286,41 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds) {
         step(F1, F0, kb + 1);
     }
     step(F0, F1, nkb - 2);
+    // the scales' exponents: every copy has landed, so these loads are the
+    // only ones in flight and the last stage's MFMAs hide them
+    ScaleExps<TM, kTileN2, threads2(TM)> se;
+    se.load(C, (int64_t)I * TM, (int64_t)J * kTileN2, tid);
+    __builtin_amdgcn_sched_barrier(0);
     mfma_rows(F1, 0);
     mfma_rows(F1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    se.store(sexp, tid);
 
     // epilogue through LDS, one output at a time
-    stage_out<TM>(C, I, J, ap, lds, false);
-    stage_out<TM>(C, I, J, aq, lds, true);
+    stage_out<TM>(C, I, J, ap, lds, sexp, false);
+    stage_out<TM>(C, I, J, aq, lds, sexp, true);
 }
 
+// Occupancy: two workgroups of 4 waves per CU for TM = 128, one of 8 for
+// TM = 256 -- two waves per SIMD, so at most 256 VGPRs each.
 template <int P, int TM>
-__global__ __launch_bounds__(threads2(TM), 512 / TM) void corr2_kernel(CorrJob C) {
+__global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_kernel(CorrJob C) {
     __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
+    __shared__ int sexp[TM + 2 * kTileN2];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
     if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
     else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
-    corr2_tile<P, TM>(C, I, J, lds);
+    corr2_tile<P, TM>(C, I, J, lds, sexp);
 }
 
 template <int P, int TM>
-__global__ __launch_bounds__(threads2(TM), 512 / TM) void corr2_persistent_kernel(const CorrJob* jobs,
+__global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kernel(const CorrJob* jobs,
                                                                        const int64_t* tile_start,
                                                                        int count, int64_t total,
                                                                        int* counter) {
     __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
+    __shared__ int sexp[TM + 2 * kTileN2];
     __shared__ int64_t s_t;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
@@ -1333,18 +1340,19 @@ __global__ __launch_bounds__(threads2(TM), 512 / TM) void corr2_persistent_kerne
         const CorrJob C = jobs[lo];
         int I, J;
         decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
-        corr2_tile<P, TM>(C, I, J, lds);
+        corr2_tile<P, TM>(C, I, J, lds, sexp);
     }
 }
 
 template <int P, int FM, int FN>
 __global__ __launch_bounds__(256) void corr_kernel(CorrJob C) {
     extern __shared__ __attribute__((aligned(16))) char corr_lds[];
+    __shared__ int sexp[32 * FM + 64 * FN];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
     if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
     else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
-    corr_tile<P, FM, FN>(C, I, J, corr_lds);
+    corr_tile<P, FM, FN>(C, I, J, corr_lds, sexp);
 }
 
 // Persistent batched contraction: workgroups take tiles from a global ticket
@@ -1355,6 +1363,7 @@ __global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* job
                                                                int count, int64_t total,
                                                                int* counter) {
     extern __shared__ __attribute__((aligned(16))) char corr_lds[];
+    __shared__ int sexp[32 * FM + 64 * FN];
     __shared__ int64_t s_t;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
@@ -1371,7 +1380,7 @@ __global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* job
         const CorrJob C = jobs[lo];
         int I, J;
         decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
-        corr_tile<P, FM, FN>(C, I, J, corr_lds);
+        corr_tile<P, FM, FN>(C, I, J, corr_lds, sexp);
     }
 }
 

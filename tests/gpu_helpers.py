@@ -34,6 +34,30 @@ def unpack_upper(p, n):
     return full
 
 
+def aligned_row_starts(n):
+    """Row starts of the UPPER_ALIGNED layout from its definition: row i holds
+    the columns 32 floor(i/32) .. N32-1 (N32 = n rounded up to 32), rows stored
+    one after another.  Returns (starts with the total appended, first columns)."""
+    n32 = -(-n // 32) * 32
+    first = 32 * (np.arange(n, dtype=np.int64) // 32)
+    lens = n32 - first
+    return np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), first
+
+
+def unpack_upper_aligned(p, n):
+    """Upper-triangle matrices (zeros below) and the mask of padding slots
+    from an UPPER_ALIGNED plane."""
+    p = np.asarray(p)
+    starts, first = aligned_row_starts(n)
+    full = np.zeros((n, n), dtype=p.dtype)
+    pad = np.ones(len(p), dtype=bool)
+    for i in range(n):
+        a = starts[i] + (i - first[i])
+        full[i, i:] = p[a:a + n - i]
+        pad[a:a + n - i] = False
+    return full, pad
+
+
 def packed_index(i, j, n):
     i = np.asarray(i, dtype=np.int64)
     j = np.asarray(j, dtype=np.int64)

@@ -21,10 +21,13 @@ pytestmark = pytest.mark.skipif(not os.path.exists(B.LIB_PATH),
 
 
 def declared_functions():
+    """Functions the library exports: every corr2d_* declared in the header
+    except the static inline layout helpers, which live in the header."""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    inline = set(re.findall(r"static inline \w+ (corr2d_[a-z_]+)\s*\(", text))
     names = re.findall(r"\b(corr2d_[a-z_]+)\s*\(", text)
-    return sorted(set(names))
+    return sorted(set(names) - inline)
 
 
 def test_header_declares_the_boundary():
@@ -117,6 +120,8 @@ def _plan_status(**kw):
     (dict(in_dtype=4), B.EINVAL),
     (dict(norm_mode=2, norm_value=float("nan")), B.EINVAL),
     (dict(n2=100, out_layout=1), B.EINVAL),
+    (dict(n2=100, out_layout=2), B.EINVAL),
+    (dict(out_layout=2), B.OK),
     (dict(prec=5, flags=B.FLAG_NO_PER_BAND_SCALE), B.EUNSUPPORTED),
     (dict(flags=0x100), B.EINVAL),
     (dict(tile=7), B.EINVAL),
@@ -230,3 +235,63 @@ def test_interpolation_plan_workspace_and_batched_rejected():
     d = B.corr2d_desc_init(prec="f32", interp="linear", t_in=[0.0, 1.0, 3.0])
     s, _ = B.corr2d_batched_plan(d, [(3, 100, 0, 0, 0)], check=False)
     assert s == B.EUNSUPPORTED
+
+
+def _aligned_layout_by_definition(n):
+    """Row starts of the UPPER_ALIGNED layout from its definition: row i covers
+    the columns 32 floor(i/32) .. N32-1, rows stored one after another."""
+    n32 = -(-n // 32) * 32
+    lens = [n32 - 32 * (i // 32) for i in range(n)]
+    starts = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return starts, lens, n32
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 63, 64, 65, 100, 257, 1000])
+def test_upper_aligned_layout_matches_definition(n):
+    starts, lens, n32 = _aligned_layout_by_definition(n)
+    i, j = np.triu_indices(n)
+    idx = B.upper_aligned_index(i, j, n)
+    assert np.array_equal(idx, starts[i] + j - 32 * (i // 32))
+    assert np.all(starts[:-1] % 32 == 0)                 # every row on a 32-element boundary
+    assert len(np.unique(idx)) == len(idx)               # one slot per entry
+    assert idx.min() >= 0 and idx.max() < starts[-1]
+    assert B.upper_aligned_elements(n) == starts[-1] == sum(lens)
+    assert B.out_elements("upper_aligned", n) == starts[-1]
+    # padding bound stated in the header: at most 62 slots per row
+    assert starts[-1] - n * (n + 1) // 2 <= 62 * n
+
+
+def test_upper_aligned_header_helpers(tmp_path):
+    # the static inline helpers of the C header against the definition
+    cases = [(n, i, j) for n in (1, 33, 100, 16384, 70001) for i, j in
+             ((0, 0), (0, n - 1), (n // 3, n // 2), (n - 1, n - 1), (min(31, n - 1), n - 1))]
+    prog = "#include <stdio.h>\n#include \"corr2d.h\"\nint main(void){\n"
+    for n, i, j in cases:
+        prog += f'printf("%lld\\n", (long long)corr2d_upper_aligned_index({i}, {j}, {n}));\n'
+    for n in (1, 33, 100, 16384, 70001):
+        prog += f'printf("%lld\\n", (long long)corr2d_upper_aligned_elements({n}));\n'
+    prog += "return 0;}\n"
+    c = tmp_path / "a.c"
+    c.write_text(prog)
+    exe = tmp_path / "a"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I" + os.path.dirname(HEADER), str(c),
+                    "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = []
+    for n, i, j in cases:
+        n32 = -(-n // 32) * 32
+        start = sum(n32 - 32 * (k // 32) for k in range(i))
+        want.append(start + j - 32 * (i // 32))
+    for n in (1, 33, 100, 16384, 70001):
+        n32 = -(-n // 32) * 32
+        want.append(sum(n32 - 32 * (k // 32) for k in range(n)))
+    assert got == want
+
+
+def test_batched_out_elements_upper_aligned():
+    d = B.corr2d_desc_init(prec="f32", out_layout="upper_aligned")
+    e300 = B.upper_aligned_elements(300)
+    items = [(11, 300, 0, 0, 0), (64, 1000, 11 * 300, 0, e300)]
+    _, h = B.corr2d_batched_plan(d, items)
+    assert B.corr2d_plan_get_info(h).out_elements == e300 + B.upper_aligned_elements(1000)
+    B.corr2d_plan_destroy(h)

@@ -14,7 +14,8 @@ import oracle
 from paper_1808_00685_amd import binding as B
 from paper_1808_00685_amd import synth
 
-from .gpu_helpers import TOL, check_homo_structure, packed_index, rel_fro, unpack_upper
+from .gpu_helpers import (TOL, check_homo_structure, packed_index, rel_fro, unpack_upper,
+                          unpack_upper_aligned)
 
 pytestmark = pytest.mark.gpu
 
@@ -139,9 +140,95 @@ def test_upper_packed_layout(gpu, prec):
     assert np.all(np.diag(Q) == 0)
 
 
+def _homo_nan_filled(S, dev, **kw):
+    """Homocorrelation into NaN-filled outputs (to see which slots are written)."""
+    import torch
+    m, n = S.shape
+    prec = kw.get("prec", "split_bf16")
+    out = "f64" if prec == "f64" else "f32"
+    plan = B.Plan(m=m, n1=n, n2=0, in_dtype="f64", out_dtype=out, **kw)
+    numel = B.out_elements(B.LAYOUT_NAMES[plan.desc.out_layout], n)
+    tdt = torch.float64 if out == "f64" else torch.float32
+    phi = torch.full((numel,), float("nan"), dtype=tdt, device=dev)
+    psi = torch.full((numel,), float("nan"), dtype=tdt, device=dev)
+    ws = plan.workspace(dev)
+    B.corr2d_homo(plan.handle, _t(S, dev), None, phi, psi, ws)
+    return _np(phi), _np(psi), plan
+
+
+@pytest.mark.parametrize("prec,tile", [("f64", 1), ("f32", 1), ("f32", 2), ("fp8_e4m3", 1),
+                                       ("fp8_e4m3", 2), ("split_bf16", 2), ("split_bf16", 3),
+                                       ("bf16", 3), ("f16", 2)])
+@pytest.mark.parametrize("n", [1, 33, 333])
+def test_upper_aligned_layout(gpu, prec, tile, n):
+    # every kernel family writes the row-aligned triangle: entries j >= i at
+    # the layout's offsets, padding slots untouched
+    m = 21
+    S = _rand(m, n, 12 + n)
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, _ = _homo_nan_filled(S, gpu, prec=prec, tile=tile, out_layout="upper_aligned")
+    assert phi.shape == (B.upper_aligned_elements(n),)
+    P, pad = unpack_upper_aligned(phi, n)
+    Q, _ = unpack_upper_aligned(psi, n)
+    assert np.all(np.isnan(phi[pad])) and np.all(np.isnan(psi[pad]))
+    assert not np.any(np.isnan(phi[~pad])) and not np.any(np.isnan(psi[~pad]))
+    iu = np.triu_indices(n)
+    assert rel_fro(P[iu], phi_o[iu]) <= TOL[prec]
+    if n > 1:
+        assert rel_fro(Q[iu], psi_o[iu]) <= TOL[prec]
+    assert np.all(np.diag(Q) == 0)
+
+
+def test_upper_aligned_equals_packed_bitwise(gpu):
+    # the layouts differ only in addressing: the same plan settings give the
+    # same values in both
+    m, n = 64, 1500
+    S = _rand(m, n, 21)
+    for prec in ("split_bf16", "f32"):
+        pa, qa, _ = _homo_nan_filled(S, gpu, prec=prec, out_layout="upper_aligned")
+        pp, qp, _ = _homo_nan_filled(S, gpu, prec=prec, out_layout="upper_packed")
+        A, _ = unpack_upper_aligned(pa, n)
+        iu = np.triu_indices(n)
+        assert np.array_equal(A[iu], unpack_upper(pp, n)[iu])
+        A, _ = unpack_upper_aligned(qa, n)
+        assert np.array_equal(A[iu], unpack_upper(qp, n)[iu])
+
+
+def test_batched_upper_aligned(gpu):
+    # batched sets written in the aligned layout at their own offsets
+    import torch
+    sets = [_rand(9, 70, 31), _rand(40, 333, 32), _rand(3, 32, 33)]
+    items, ycat, oo, io = [], [], 0, 0
+    for S in sets:
+        m, n = S.shape
+        items.append((m, n, io, 0, oo))
+        ycat.append(S.ravel())
+        io += m * n
+        oo += B.upper_aligned_elements(n) + 5        # offsets need not be aligned
+    plan = B.Plan(prec="f32", out_layout="upper_aligned", in_dtype="f64", out_dtype="f32",
+                  items=items)
+    assert plan.info.out_elements == items[-1][4] + B.upper_aligned_elements(sets[-1].shape[1])
+    y = _t(np.concatenate(ycat), gpu)
+    phi = torch.full((oo,), float("nan"), dtype=torch.float32, device=gpu)
+    psi = torch.full((oo,), float("nan"), dtype=torch.float32, device=gpu)
+    ws = plan.workspace(gpu)
+    B.corr2d_batched(plan.handle, y, phi, psi, ws)
+    gp, gq = _np(phi), _np(psi)
+    for S, it in zip(sets, items):
+        n = S.shape[1]
+        e = B.upper_aligned_elements(n)
+        P, pad = unpack_upper_aligned(gp[it[4]:it[4] + e], n)
+        Q, _ = unpack_upper_aligned(gq[it[4]:it[4] + e], n)
+        phi_o, psi_o = oracle.corr2d(S)
+        iu = np.triu_indices(n)
+        assert rel_fro(P[iu], phi_o[iu]) <= TOL["f32"]
+        assert rel_fro(Q[iu], psi_o[iu]) <= TOL["f32"]
+        assert np.all(np.isnan(gp[it[4]:it[4] + e][pad]))
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
 @pytest.mark.parametrize("tile", [2, 3])
-@pytest.mark.parametrize("layout", ["full", "upper_packed"])
+@pytest.mark.parametrize("layout", ["full", "upper_packed", "upper_aligned"])
 def test_lds_staged_tile_shapes(gpu, prec, tile, layout):
     # both tile shapes of the LDS-staged kernel (256 x 128 and 128 x 128),
     # with ragged edges and several diagonal-crossing tiles
@@ -151,8 +238,11 @@ def test_lds_staged_tile_shapes(gpu, prec, tile, layout):
     phi, psi, plan = _homo(S, gpu, prec=prec, layout=layout, tile=tile)
     info = plan.info
     assert (info.tile_m, info.tile_n) == ((256, 128) if tile == 2 else (128, 128))
-    if layout == "upper_packed":
-        phi, psi = unpack_upper(phi, n), unpack_upper(psi, n)
+    if layout != "full":
+        if layout == "upper_packed":
+            phi, psi = unpack_upper(phi, n), unpack_upper(psi, n)
+        else:
+            phi, psi = unpack_upper_aligned(phi, n)[0], unpack_upper_aligned(psi, n)[0]
         iu = np.triu_indices(n)
         assert rel_fro(phi[iu], phi_o[iu]) <= TOL[prec]
         assert rel_fro(psi[iu], psi_o[iu]) <= TOL[prec]

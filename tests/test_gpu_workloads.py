@@ -64,6 +64,47 @@ def test_large_homo_sampled(gpu, large, prec, basis, tol):
     del phi, psi, ws
 
 
+def test_large_upper_aligned_equals_packed(gpu, large):
+    """The bench's launch in both upper layouts at m=256, n=16384: every
+    aligned-layout entry equals the packed one bit for bit (so the sampled
+    oracle check above covers both), and exactly the padding slots stay
+    unwritten."""
+    import torch
+    S = large[0]
+    m, n = S.shape
+    y = torch.as_tensor(S, device=gpu)
+    outs = {}
+    for layout in ("upper_packed", "upper_aligned"):
+        plan = B.Plan(m=m, n1=n, n2=0, prec="split_bf16", out_layout=layout, in_dtype="f64",
+                      out_dtype="f32")
+        numel = B.out_elements(layout, n)
+        phi = torch.full((numel,), float("nan"), dtype=torch.float32, device=gpu)
+        psi = torch.full((numel,), float("nan"), dtype=torch.float32, device=gpu)
+        ws = plan.workspace(gpu)
+        B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
+        torch.cuda.synchronize()
+        outs[layout] = (phi, psi)
+        del ws, plan
+    # packed order -> aligned slots, from the layout's definition (row starts
+    # are cumulative row lengths N32 - 32 floor(i/32))
+    ii = torch.arange(n, device=gpu, dtype=torch.int64)
+    first = 32 * (ii // 32)
+    alen = (n + 31) // 32 * 32 - first
+    astart = torch.cumsum(alen, 0) - alen
+    plen = n - ii
+    rows = torch.repeat_interleave(ii, plen)
+    pstart = torch.cumsum(plen, 0) - plen
+    cols = torch.arange(rows.numel(), device=gpu, dtype=torch.int64) - pstart[rows] + rows
+    aidx = astart[rows] + cols - first[rows]
+    del cols
+    for k in range(2):
+        pk, al = outs["upper_packed"][k], outs["upper_aligned"][k]
+        assert not torch.isnan(pk).any()
+        assert torch.equal(al[aidx], pk)
+        assert int(torch.isnan(al).sum()) == al.numel() - n * (n + 1) // 2
+    del outs, aidx, rows
+
+
 @pytest.fixture(scope="module")
 def hetero_data():
     S1, S2, meta = synth.workload_hetero()
