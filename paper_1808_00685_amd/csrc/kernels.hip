@@ -1129,7 +1129,37 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
     const int wi = w >> 1, wj = w & 1, g = lane >> 5;
     const int64_t i0 = (int64_t)I * TM, j0 = (int64_t)J * kTileN2;
     const bool diag = C.homo && j0 <= i0 + TM - 1;
-    lds_barrier();   // previous readers of the LDS are done
+    lds_barrier();   // previous readers of the LDS are done (and the scale table is visible)
+    if (C.homo && C.layout == L_UPPER_ALIGNED && i0 + TM <= C.n1 && j0 + kTileN2 <= C.n2 && !diag) {
+        // Row-aligned upper layout, interior tile: straight from the
+        // accumulators.  Register r of a 32 x 32 block holds 32 consecutive
+        // columns of two rows, whole aligned 128-byte lines here, so no
+        // staging through LDS is needed.  The block's 32 rows lie in one
+        // 32-row band of the layout and share its row length.
+        float* out = (float*)(psi ? C.psi : C.phi);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int64_t ia = i0 + wi * 64 + a * 32;
+            const int64_t base = aligned_row_base(ia, C.n1);
+            const uint32_t len = (((uint32_t)C.n1 + 31u) & ~31u) - 32u * (uint32_t)(ia >> 5);
+            int4 re[4];   // row exponents of rows ia + 8k + 4g .. + 3
+#pragma unroll
+            for (int k = 0; k < 4; ++k) re[k] = *(const int4*)(sexp + wi * 64 + a * 32 + 8 * k + 4 * g);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int jl = wj * 64 + b * 32 + (lane & 31);
+                const double fc = ldexp(C.c, sexp[TM + (psi ? kTileN2 : 0) + jl]);
+                float* o = out + base + j0 + jl;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int k = r >> 2, q = r & 3;
+                    const int e = q == 0 ? re[k].x : q == 1 ? re[k].y : q == 2 ? re[k].z : re[k].w;
+                    o[mul64(8 * k + 4 * g + q, len)] = ldexpf((float)((double)acc[a][b][r] * fc), e);
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const int jl = wj * 64 + b * 32 + (lane & 31);

@@ -70,13 +70,14 @@ def write_table(lines, path, header):
 
 
 def time_tile(B, torch, prec, m, n, tile, ev, reps=5):
-    """Mean contraction-kernel time (ms) of one homocorrelation plan."""
+    """Mean contraction-kernel time (ms) of one homocorrelation plan (row-aligned
+    upper triangle, the benchmark's layout)."""
     import numpy as np
     dev = torch.device("cuda:0")
-    plan = B.Plan(m=m, n1=n, n2=0, prec=prec, out_layout="upper_packed", in_dtype="f64",
+    plan = B.Plan(m=m, n1=n, n2=0, prec=prec, out_layout="upper_aligned", in_dtype="f64",
                   out_dtype="f64" if prec == "f64" else "f32", tile=tile)
     y = torch.randn(m, n, dtype=torch.float64, device=dev) + 3.0
-    numel = n * (n + 1) // 2
+    numel = B.out_elements("upper_aligned", n)
     odt = torch.float64 if prec == "f64" else torch.float32
     phi = torch.empty(numel, dtype=odt, device=dev)
     psi = torch.empty(numel, dtype=odt, device=dev)
