@@ -468,28 +468,38 @@ __global__ __launch_bounds__(256) void center_kernel(Src src) {
 // =========================================================================
 // Transform GEMM: [A | B] = Yc^T T^T, then scale, round and pack
 // =========================================================================
+// Four consecutive contraction elements (k .. k+3 of one row, idx a multiple
+// of 4, so one vector store per plane) rounded to the operand format: split
+// BF16 stores hi = RNE(x) and lo = RNE(x - hi).
 template <int P>
-__device__ inline void store_operand(const PrepJob& J, void* p0, void* p1, int64_t idx, float x) {
-    if (P == P_F32) {
-        ((float*)p0)[idx] = x;
-    } else if (P == P_SPLIT) {
-        const uint16_t hi = bf16_rne(x);
-        const uint16_t lo = bf16_rne(x - bf16_val(hi));
-        ((uint16_t*)p0)[idx] = hi;
-        ((uint16_t*)p1)[idx] = lo;
-    } else if (P == P_BF16) {
-        ((uint16_t*)p0)[idx] = bf16_rne(x);
-    } else if (P == P_F16) {
-        ((_Float16*)p0)[idx] = (_Float16)x;
-    } else if (P == P_FP8) {
-        ((uint8_t*)p0)[idx] = fp8_e4m3_rne(x);
+__device__ inline void store_operand4(void* p0, void* p1, int64_t idx, const float (&x)[4]) {
+    if constexpr (P == P_F32) {
+        *(float4*)((float*)p0 + idx) = make_float4(x[0], x[1], x[2], x[3]);
+    } else if constexpr (P == P_SPLIT || P == P_BF16) {
+        uint16_t hi[4], lo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            hi[q] = bf16_rne(x[q]);
+            lo[q] = bf16_rne(x[q] - bf16_val(hi[q]));
+        }
+        *(uint2*)((uint16_t*)p0 + idx) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
+        if constexpr (P == P_SPLIT)
+            *(uint2*)((uint16_t*)p1 + idx) = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+    } else if constexpr (P == P_F16) {
+        typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+        *(h4v*)((_Float16*)p0 + idx) = h4v{(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3]};
+    } else if constexpr (P == P_FP8) {
+        *(uint32_t*)((uint8_t*)p0 + idx) = fp8_e4m3_rne(x[0]) | ((uint32_t)fp8_e4m3_rne(x[1]) << 8) |
+                                           ((uint32_t)fp8_e4m3_rne(x[2]) << 16) | ((uint32_t)fp8_e4m3_rne(x[3]) << 24);
     }
 }
 
-// T64: transform arithmetic in FP64 (operands F64) or FP32 (all others).
+// FP64 transform GEMM (the FP64 contraction's operands, no rounding to a
+// narrower format): 64 x 64 workgroup tiles, each wave 32 x 32 (2 x 2 blocks
+// of v_mfma_f64_16x16x4f64).
 template <int P, class Src>
 __global__ __launch_bounds__(256) void transform_kernel(Src src) {
-    constexpr bool T64 = (P == P_F64);
+    static_assert(P == P_F64, "the reduced precisions use transform32_kernel");
     int lb;
     const PrepJob J = src.get(blockIdx.x, lb);
     const int row_tiles = J.rows_pad / kTransformTile;
@@ -500,91 +510,53 @@ __global__ __launch_bounds__(256) void transform_kernel(Src src) {
     const int64_t r0 = (int64_t)br * kTransformTile + (wave & 1) * 32;
     if (r0 >= J.rows_pad) return;
 
-    if constexpr (T64) {
-        d4 acc[2][2];
+    d4 acc[2][2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
-        const double* Y = (const double*)J.yt;
-        const double* T = (const double*)J.table;
-        for (int k0 = 0; k0 < J.kt; k0 += 16) {
-            d4 fa[2], fb[2];
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+    const double* Y = (const double*)J.yt;
+    const double* T = (const double*)J.table;
+    for (int k0 = 0; k0 < J.kt; k0 += 16) {
+        d4 fa[2], fb[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) fa[a] = *(const d4*)(Y + (i0 + a * 16 + row16) * J.kt + k0 + kg * 4);
+        for (int a = 0; a < 2; ++a) fa[a] = *(const d4*)(Y + (i0 + a * 16 + row16) * J.kt + k0 + kg * 4);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) fb[b] = *(const d4*)(T + (r0 + b * 16 + row16) * J.kt + k0 + kg * 4);
+        for (int b = 0; b < 2; ++b) fb[b] = *(const d4*)(T + (r0 + b * 16 + row16) * J.kt + k0 + kg * 4);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a][s], fb[b][s], acc[a][b], 0, 0, 0);
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int64_t r = r0 + b * 16 + row16;
-                if (r >= 2 * (int64_t)J.kp) continue;
-                const bool isB = r >= J.kp;
-                if (isB && !J.need_b) continue;
-                const int64_t k = isB ? r - J.kp : r;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t i = i0 + a * 16 + kg + 4 * q;   // FP64 accumulator rows
-                    double* dst = (double*)(isB ? J.B0 : J.A0);
-                    dst[i * J.kp + k] = acc[a][b][q];
-                }
-            }
-    } else {
-        f4 acc[2][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = f4{0, 0, 0, 0};
-        const float* Y = (const float*)J.yt;
-        const float* T = (const float*)J.table;
-        for (int k0 = 0; k0 < J.kt; k0 += 16) {
-            f4 fa[2], fb[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) fa[a] = *(const f4*)(Y + (i0 + a * 16 + row16) * J.kt + k0 + kg * 4);
-#pragma unroll
-            for (int b = 0; b < 2; ++b) fb[b] = *(const f4*)(T + (r0 + b * 16 + row16) * J.kt + k0 + kg * 4);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][s], fb[b][s], acc[a][b], 0, 0, 0);
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int64_t r = r0 + b * 16 + row16;
-                if (r >= 2 * (int64_t)J.kp) continue;
-                const bool isB = r >= J.kp;
-                if (isB && !J.need_b) continue;
-                const int64_t k = isB ? r - J.kp : r;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t i = i0 + a * 16 + kg * 4 + q;
-                    const float s = isB ? J.sB[i] : J.sA[i];
-                    const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
-                    store_operand<P>(J, isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx,
-                                     acc[a][b][q] * s);
-                }
-            }
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a][s], fb[b][s], acc[a][b], 0, 0, 0);
     }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t r = r0 + b * 16 + row16;
+            if (r >= 2 * (int64_t)J.kp) continue;
+            const bool isB = r >= J.kp;
+            if (isB && !J.need_b) continue;
+            const int64_t k = isB ? r - J.kp : r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t i = i0 + a * 16 + kg + 4 * q;   // FP64 accumulator rows
+                double* dst = (double*)(isB ? J.B0 : J.A0);
+                dst[i * J.kp + k] = acc[a][b][q];
+            }
+        }
 }
 
 // FP32 transform GEMM for the reduced precisions.  Workgroup tile: 64
 // spectral points x 256 transform rows; each wave owns 64 x 64 (4 x 4 blocks
 // of v_mfma_f32_16x16x4f32) and prefetches the next K step's fragments while
-// the current step's MFMAs run.
+// the current step's MFMAs run.  The table rows are the MFMA's A operand, so
+// accumulator register q of lane l holds transform row 4(l/16) + q of point
+// l%16: four consecutive contraction elements of one operand row, which the
+// epilogue stores with one vector store per plane (16 lanes cover a
+// contiguous run of the blocked layout).
 constexpr int kT32Cols = 256;
 
 template <int P, class Src>
@@ -597,7 +569,18 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
     const int row16 = lane & 15, kg = lane >> 4;
     const int64_t i0 = (int64_t)bi * 64;
     const int64_t r0 = (int64_t)br * kT32Cols + wave * 64;
-    if (r0 >= J.rows_pad) return;
+    // The per-band scales of the workgroup's 64 spectral points (A then B),
+    // read once ahead of the K loop and kept in LDS: read between the
+    // epilogue's stores, each load's wait would also wait for every store
+    // before it (vmcnt counts both).
+    // A set whose B operand is not needed (the left set of a
+    // heterocorrelation) has no B scales: sB is null then.
+    __shared__ float s_scale[2][64];
+    const int st = threadIdx.x;
+    const float* sp = st < 64 ? J.sA : J.sB;
+    const float scv = (st < 128 && sp != nullptr) ? sp[i0 + (st & 63)] : 0.0f;
+    // waves past the transform's rows skip the work but still take the barrier
+    const bool active = r0 < J.rows_pad;
     const float* Y = (const float*)J.yt;
     const float* T = (const float*)J.table;
     const float* yrow[4];
@@ -613,12 +596,14 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
     f4 fa[4], fb[4];
+    if (active) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        fa[a] = *(const f4*)(yrow[a]);
-        fb[a] = *(const f4*)(trow[a]);
+        for (int a = 0; a < 4; ++a) {
+            fa[a] = *(const f4*)(yrow[a]);
+            fb[a] = *(const f4*)(trow[a]);
+        }
     }
-    for (int k0 = 0; k0 < J.kt; k0 += 16) {
+    for (int k0 = 0; active && k0 < J.kt; k0 += 16) {
         f4 na[4], nb[4];
         const bool more = k0 + 16 < J.kt;
         if (more) {
@@ -634,7 +619,7 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][s], fb[b][s], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b][s], fa[a][s], acc[a][b], 0, 0, 0);
         if (more) {
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
@@ -643,22 +628,27 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
             }
         }
     }
+    if (st < 128) s_scale[st >> 6][st & 63] = scv;
+    __syncthreads();
+    if (!active) return;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int64_t r = r0 + b * 16 + row16;
-        if (r >= 2 * (int64_t)J.kp) continue;
-        const bool isB = r >= J.kp;
+        // rows r0 + 16 b .. + 15 are all A rows or all B rows (K is a
+        // multiple of 16); this lane holds rows rb .. rb + 3
+        const int64_t rb0 = r0 + b * 16;
+        if (rb0 >= 2 * (int64_t)J.kp) continue;
+        const bool isB = rb0 >= J.kp;
         if (isB && !J.need_b) continue;
-        const int64_t k = isB ? r - J.kp : r;
+        const int64_t k = (isB ? rb0 - J.kp : rb0) + kg * 4;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t i = i0 + a * 16 + kg * 4 + q;
-                const float sc = isB ? J.sB[i] : J.sA[i];
-                const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
-                store_operand<P>(J, isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx, acc[a][b][q] * sc);
-            }
+        for (int a = 0; a < 4; ++a) {
+            const int il = a * 16 + row16;
+            const int64_t i = i0 + il;
+            const float sc = s_scale[isB ? 1 : 0][il];
+            const float x[4] = {acc[a][b][0] * sc, acc[a][b][1] * sc, acc[a][b][2] * sc, acc[a][b][3] * sc};
+            const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
+            store_operand4<P>(isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx, x);
+        }
     }
 }
 
