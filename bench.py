@@ -49,6 +49,74 @@ def rel_fro(g, o):
     return float(np.linalg.norm(g - o) / np.linalg.norm(o))
 
 
+# Table 1 of the paper (Sec. 4.3): mean time of one corr2d() homocorrelation
+# in seconds, R package corr2D 0.1.12 on an Intel Core i5-2450M (Windows 7),
+# by cores and m, for n = 200, 400, 600, 1000, 4000, 8000.  Context only:
+# other hardware, FP64 complex arithmetic, full n x n result.
+TABLE1_N = (200, 400, 600, 1000, 4000, 8000)
+TABLE1_S = {
+    1: {5: (0.36, 0.50, 0.65, 1.05, 5.55, 16.37), 10: (0.36, 0.50, 0.66, 1.10, 5.76, 18.21),
+        20: (0.36, 0.50, 0.67, 1.11, 6.17, 18.61), 100: (0.63, 0.98, 0.92, 1.33, 9.74, 33.04),
+        500: (0.48, 0.82, 1.23, 2.57, 26.53, 105.23)},
+    2: {5: (0.56, 0.69, 0.80, 1.18, 5.03, 15.09), 10: (0.62, 0.69, 0.83, 1.18, 5.16, 15.88),
+        20: (0.56, 0.68, 0.82, 1.21, 5.40, 16.87), 100: (0.59, 0.73, 0.89, 1.33, 7.50, 27.01),
+        500: (0.66, 0.92, 1.27, 2.15, 18.46, 74.43)},
+    4: {5: (1.00, 1.11, 1.21, 1.62, 5.45, 15.49), 10: (0.99, 1.09, 1.22, 1.59, 5.55, 16.11),
+        20: (0.99, 1.09, 1.23, 1.63, 5.88, 17.20), 100: (1.02, 1.13, 1.31, 1.73, 7.82, 26.81),
+        500: (1.10, 1.42, 1.70, 2.62, 18.33, 72.34)},
+}
+
+
+def paper_context():
+    """The paper's fastest whole-call rate (n^2 entries of the full complex
+    matrix per second), for context next to this GPU's numbers."""
+    best = None
+    for cores, rows in TABLE1_S.items():
+        for m, secs in rows.items():
+            for n, sec in zip(TABLE1_N, secs):
+                r = n * n / sec
+                if best is None or r > best[0]:
+                    best = (r, cores, m, n, sec)
+    r, cores, m, n, sec = best
+    return {"entries_per_s": r, "definition": "n^2 / mean corr2d() time (full complex matrix)",
+            "config": f"m={m}, n={n}, {cores} cores, {sec} s",
+            "hardware": "Intel Core i5-2450M, R corr2D 0.1.12, FP64 (Table 1 of the paper)",
+            "kind": "context, not the target"}
+
+
+def table1_sweep(B, torch, synth, dev, reps=5):
+    """The paper's Table 1 grid on this GPU: full n x n homocorrelation, FP64
+    and FP32 (whole call, inputs resident), next to the paper's seconds.
+    Inputs: seeded band spectra (8 Lorentzians), a stand-in for the paper's
+    simulated reaction data, whose parameters it does not give."""
+    out = []
+    for m in (5, 10, 20, 100, 500):
+        for ni, n in enumerate(TABLE1_N):
+            S, _ = synth.bands(m, n, 8, seed=synth.BASE_SEED + 20000 + 10 * m + ni)
+            y = torch.as_tensor(S, device=dev)
+            for prec in ("f64", "f32"):
+                out_dtype = "f64" if prec == "f64" else "f32"
+                plan = B.Plan(m=m, n1=n, n2=0, prec=prec, out_layout="full", in_dtype="f64",
+                              out_dtype=out_dtype)
+                tdt = torch.float64 if prec == "f64" else torch.float32
+                phi = torch.empty(n * n, dtype=tdt, device=dev)
+                psi = torch.empty(n * n, dtype=tdt, device=dev)
+                ws = plan.workspace(dev)
+                B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
+                torch.cuda.synchronize()
+                sec = (time.perf_counter() - t0) / reps
+                paper = {c: TABLE1_S[c][m][ni] for c in TABLE1_S}
+                out.append({"m": m, "n": n, "prec": prec, "ms_per_call": sec * 1e3,
+                            "paper_s": paper, "ratio_to_best_paper": min(paper.values()) / sec})
+                del phi, psi, ws, plan
+            torch.cuda.empty_cache()
+    return out
+
+
 LAYOUT_TEXT = {"upper_aligned": "rows aligned to 128 bytes",
                "upper_packed": "packed rows"}
 
@@ -113,10 +181,11 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     return res
 
 
-def measured_traffic(kernel_tag="corr2_split_m256_n16384"):
-    """HBM bytes per launch of the contraction kernel from the committed PMC
-    record (FETCH_SIZE and WRITE_SIZE, each scaled by a 1 GiB copy), or None
-    when the kernel source has changed since the counters were taken."""
+def profile_record(kernel_tag="corr2_split_m256_n16384"):
+    """The committed PMC record of the contraction kernel (HBM bytes from
+    FETCH_SIZE and WRITE_SIZE, each scaled by a 1 GiB copy; MFMA operations
+    from SQ_INSTS_VALU_MFMA_MOPS_BF16), or None when the kernel source has
+    changed since the counters were taken."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
     src = os.path.join(ROOT, "paper_1808_00685_amd", "csrc", "kernels.hip")
@@ -127,7 +196,7 @@ def measured_traffic(kernel_tag="corr2_split_m256_n16384"):
         return None
     if rec.get("kernels_hip_sha256") != sha:
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec
 
 
 def cpu_baseline(oracle, S, target_s):
@@ -326,6 +395,8 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--layout", default="upper_aligned", choices=["upper_aligned", "upper_packed"],
                     help="storage of the upper triangle in the headline line")
+    ap.add_argument("--table1", action="store_true",
+                    help="instead of the benchmark line, time the paper's Table 1 grid (FP64, FP32)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -344,6 +415,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
+    if args.table1:
+        print(json.dumps({"table1": table1_sweep(B, torch, synth, dev), "paper": paper_context()}),
+              flush=True)
+        return
     m, n = args.m, args.n
     S, meta = synth.workload_large(m=m, n=n)
     sample = sample_pairs(n, 3000, 5, meta["centers"][:48])
@@ -378,6 +453,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(oracle, S, args.cpu_seconds)
 
+    prof = profile_record() if (m, n, layout) == (256, 16384, "upper_aligned") else None
     alg = main_res["alg_flops"]
     kms = main_res["kernel_ms"]
     achieved = alg / (kms * 1e-3) / 1e12
@@ -406,7 +482,8 @@ def main():
             "bound": "hbm", "kernel": f"corr2_kernel<split_bf16> ({main_res['tile']} tiles)",
             "achieved": main_res["kernel_hbm_GBps"], "peak": HBM_GBPS, "unit": "GB/s",
             "frac": main_res["kernel_hbm_GBps"] / HBM_GBPS,
-            "traffic": measured_traffic() if (m, n, layout) == (256, 16384, "upper_aligned") else None,
+            "traffic": (prof or {}).get("traffic_bytes_per_launch"),
+            "executed_flops_counted": (prof or {}).get("executed_mfma_flops_counted"),
             "kernel_ms": kms,
             "algorithmic_bytes_per_launch": main_res["kernel_bytes"],
             "algorithmic_flops_per_launch": alg,
@@ -420,6 +497,7 @@ def main():
         "error_vs_oracle": {"phi": main_res["err_phi"], "psi": main_res["err_psi"],
                             "sampled_entries": int(len(sample[0]))},
         "cpu_baseline": cpu,
+        "paper_context": paper_context(),
         "variants": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()
                       if k not in ("alg_flops", "executed_flops", "kernel_bytes")}
                      for r in variants],

@@ -194,10 +194,13 @@ def test_upper_aligned_equals_packed_bitwise(gpu):
         assert np.array_equal(A[iu], unpack_upper(qp, n)[iu])
 
 
-def test_batched_upper_aligned(gpu):
-    # batched sets written in the aligned layout at their own offsets
+@pytest.mark.parametrize("prec", ["f32", "split_bf16", "bf16"])
+def test_batched_upper_aligned(gpu, prec):
+    # batched sets written in the aligned layout at their own offsets; the
+    # 700-point set has interior tiles (stored straight from the
+    # accumulators by the persistent 16-bit kernel)
     import torch
-    sets = [_rand(9, 70, 31), _rand(40, 333, 32), _rand(3, 32, 33)]
+    sets = [_rand(9, 70, 31), _rand(40, 333, 32), _rand(3, 32, 33), _rand(24, 700, 34)]
     items, ycat, oo, io = [], [], 0, 0
     for S in sets:
         m, n = S.shape
@@ -205,7 +208,7 @@ def test_batched_upper_aligned(gpu):
         ycat.append(S.ravel())
         io += m * n
         oo += B.upper_aligned_elements(n) + 5        # offsets need not be aligned
-    plan = B.Plan(prec="f32", out_layout="upper_aligned", in_dtype="f64", out_dtype="f32",
+    plan = B.Plan(prec=prec, out_layout="upper_aligned", in_dtype="f64", out_dtype="f32",
                   items=items)
     assert plan.info.out_elements == items[-1][4] + B.upper_aligned_elements(sets[-1].shape[1])
     y = _t(np.concatenate(ycat), gpu)
@@ -221,9 +224,10 @@ def test_batched_upper_aligned(gpu):
         Q, _ = unpack_upper_aligned(gq[it[4]:it[4] + e], n)
         phi_o, psi_o = oracle.corr2d(S)
         iu = np.triu_indices(n)
-        assert rel_fro(P[iu], phi_o[iu]) <= TOL["f32"]
-        assert rel_fro(Q[iu], psi_o[iu]) <= TOL["f32"]
+        assert rel_fro(P[iu], phi_o[iu]) <= TOL[prec]
+        assert rel_fro(Q[iu], psi_o[iu]) <= TOL[prec]
         assert np.all(np.isnan(gp[it[4]:it[4] + e][pad]))
+        assert np.all(np.diag(Q) == 0)
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
