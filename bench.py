@@ -181,20 +181,30 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     return res
 
 
+def kernel_code_sha256(path):
+    """SHA-256 of a source file with its comments removed: the counters stay
+    valid across edits that change no code."""
+    import hashlib
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return hashlib.sha256(src.encode()).hexdigest()
+
+
 def profile_record(kernel_tag="corr2_split_m256_n16384"):
     """The committed PMC record of the contraction kernel (HBM bytes from
     FETCH_SIZE and WRITE_SIZE, each scaled by a 1 GiB copy; MFMA operations
-    from SQ_INSTS_VALU_MFMA_MOPS_BF16), or None when the kernel source has
+    from SQ_INSTS_VALU_MFMA_MOPS_BF16), or None when the kernel code has
     changed since the counters were taken."""
-    import hashlib
     rec_path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
     src = os.path.join(ROOT, "paper_1808_00685_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(rec_path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_code_sha256(src)
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_hip_sha256") != sha:
+    if rec.get("kernels_hip_code_sha256") != sha:
         return None
     return rec
 

@@ -10,14 +10,21 @@
 //                     (Eqs. (dynspec), (ref)), transposed so that each
 //                     spectral point's m values are contiguous; per-band
 //                     power-of-two scales from the column norm.
-//   transform_kernel  MFMA GEMM  [A | B] = Yc^T [T1 | T2]^T  (FP64 or FP32),
-//                     epilogue scales, rounds (RNE) and packs the contraction
-//                     operands, K-contiguous, zero padded.
-//   corr_kernel       MFMA GEMM over output tiles: Phi = c A1^T A2,
+//   transform_kernel, transform32_kernel
+//                     MFMA GEMM  [A | B] = Yc^T [T1 | T2]^T  (FP64, or FP32
+//                     for the reduced formats); the epilogue scales, rounds
+//                     (RNE) and packs the contraction operands, zero padded
+//                     (panel-blocked for the 16-bit formats).
+//   corr2_kernel, corr_kernel
+//                     MFMA GEMM over output tiles: Phi = c A1^T A2,
 //                     Psi = c A1^T B2 (Eq. (disint2d) evaluated as a real
 //                     contraction over the packed half spectrum), FP64
 //                     epilogue, upper-triangle tiles for homocorrelation with
-//                     exact mirror or packed stores.
+//                     exact mirror or upper-triangle stores (LDS-staged ring
+//                     and 32x32 MFMA for the 16-bit formats, register-direct
+//                     16x16 MFMA for FP64, FP32 and FP8).
+//   interp_kernel     resampling onto equidistant perturbation values
+//                     (Sec. 4.1) ahead of the centring, when asked for.
 //
 // MFMA fragment convention (16x16 family): lane l supplies row (l & 15) and
 // the contraction slice (l >> 4) of its operand; the accumulator register q
@@ -744,12 +751,13 @@ __device__ inline void lds_write_barrier() {
 // ---------------------------------------------------------------------------
 // An output tile of TM x TN values of type OT sits in LDS with a row pitch
 // of TN + 4 elements, already scaled by c / sR_j; store_tile writes it out
-// with NT threads as contiguous row runs (16-byte stores where the
-// destination allows): direct rows for heterocorrelation and the upper part
-// of a homocorrelation, the mirror of a FULL homocorrelation read transposed
-// from the same tile (Psi negated), or the rows of UPPER_PACKED.  The row
-// scale 1 / sL_i, a power of two, is applied exactly with ldexp as the rows
-// leave LDS; this equals one FP64 product unless the result is subnormal.
+// with NT threads as contiguous row runs (16-byte stores): direct rows for
+// heterocorrelation and the upper part of a homocorrelation, the mirror of a
+// FULL homocorrelation read transposed from the same tile (Psi negated), or
+// the rows of an upper-triangle layout.  The row scale 1 / sL_i, a power of
+// two, is applied exactly with ldexp as the rows leave LDS; this equals one
+// FP64 product unless the result is subnormal.  (Interior tiles of the
+// row-aligned upper layout skip LDS in the LDS-staged kernel; see stage_out.)
 
 // Exponent of a power-of-two scale.
 __device__ inline int pow2_exp(float s) { return ((__float_as_int(s) >> 23) & 0xff) - 127; }
