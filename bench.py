@@ -182,13 +182,14 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
 
 
 def kernel_code_sha256(path):
-    """SHA-256 of a source file with its comments removed: the counters stay
-    valid across edits that change no code."""
+    """SHA-256 of a source file with its comments removed and whitespace
+    collapsed: the counters stay valid across edits that change no code."""
     import hashlib
     import re
     src = open(path).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     src = re.sub(r"//[^\n]*", "", src)
+    src = " ".join(src.split())   # layout-only edits do not count either
     return hashlib.sha256(src.encode()).hexdigest()
 
 
