@@ -1372,8 +1372,11 @@ __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kerne
     }
 }
 
+// Occupancy: two workgroups per CU (at most 256 registers): with the
+// default the 128 x 128 tile grew to 400 registers and one wave per SIMD,
+// which left the fragment loads' latency unhidden.
 template <int P, int FM, int FN>
-__global__ __launch_bounds__(256) void corr_kernel(CorrJob C) {
+__global__ __launch_bounds__(256, 2) void corr_kernel(CorrJob C) {
     extern __shared__ __attribute__((aligned(16))) char corr_lds[];
     __shared__ int sexp[32 * FM + 64 * FN];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -1385,8 +1388,10 @@ __global__ __launch_bounds__(256) void corr_kernel(CorrJob C) {
 
 // Persistent batched contraction: workgroups take tiles from a global ticket
 // counter until the list (data sets in descending cost order) is exhausted.
+// The 128 x 128 tile keeps the default bound here: held to 256 registers the
+// tile loop spills.
 template <int P, int FM, int FN>
-__global__ __launch_bounds__(256) void corr_persistent_kernel(const CorrJob* jobs,
+__global__ __launch_bounds__(256, FM * FN < 16 ? 2 : 1) void corr_persistent_kernel(const CorrJob* jobs,
                                                                const int64_t* tile_start,
                                                                int count, int64_t total,
                                                                int* counter) {
