@@ -127,6 +127,10 @@ typedef enum corr2d_dtype { CORR2D_DTYPE_F64 = 0, CORR2D_DTYPE_F32 = 1 } corr2d_
 #define CORR2D_FLAG_NO_PER_BAND_SCALE 0x2u /* force scaling off (F16 only)          */
 #define CORR2D_FLAG_SEQUENTIAL 0x4u      /* batched: one launch chain per data set */
 #define CORR2D_FLAG_NO_GRAPH 0x8u        /* batched: launch directly, no hipGraph  */
+#define CORR2D_FLAG_TRANSFORM_MATMUL 0x10u /* perturbation-axis transform as the MFMA
+                                           product with the DFT table also where
+                                           the radix FFT applies (Fourier basis,
+                                           power-of-two 128 <= m <= 1024, not FP64) */
 
 typedef struct corr2d_desc {
     int64_t m;          /* perturbation steps, >= 2 (Eq. (disFT): equidistant)   */
@@ -204,6 +208,9 @@ typedef struct corr2d_plan_info {
     size_t workspace_bytes;
     int64_t items;        /* batched plans: data sets                             */
     int64_t out_elements; /* batched plans: elements of phi (and of psi) written  */
+    int32_t transform;    /* perturbation-axis transform: 0 = product with the DFT
+                             table on MFMA, 1 = radix FFT in LDS                  */
+    int32_t reserved;
 } corr2d_plan_info;
 
 /* Fill *d with defaults: FP64 input, FP32 output, SPLIT_BF16, FOURIER, NODA

@@ -28,6 +28,7 @@ FLAG_PER_BAND_SCALE = 0x1
 FLAG_NO_PER_BAND_SCALE = 0x2
 FLAG_SEQUENTIAL = 0x4
 FLAG_NO_GRAPH = 0x8
+FLAG_TRANSFORM_MATMUL = 0x10
 
 EXPORTED = [
     "corr2d_desc_init", "corr2d_plan", "corr2d_batched_plan", "corr2d_plan_destroy",
@@ -62,7 +63,7 @@ class corr2d_plan_info(ctypes.Structure):
         ("tile", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32),
         ("per_band_scale", ctypes.c_int32), ("c", ctypes.c_double),
         ("workspace_bytes", ctypes.c_size_t), ("items", ctypes.c_int64),
-        ("out_elements", ctypes.c_int64),
+        ("out_elements", ctypes.c_int64), ("transform", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -126,6 +126,7 @@ struct corr2d_plan_s {
     int group = 8;
     // single / hetero
     Geo g1, g2;
+    bool fft = false;         // radix FFT transform (else the table product)
     size_t table_off = 0;
     SetLayout s1, s2;
     size_t ws_bytes = 0;
@@ -209,7 +210,7 @@ corr2d_status check_common(const corr2d_desc* d) {
                 return fail(CORR2D_EINVAL, "t_in must be strictly increasing (t_in[%lld])", (long long)i);
         }
     }
-    if (d->flags & ~0xfu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
+    if (d->flags & ~0x1fu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
     if (d->prec == CORR2D_PREC_FP8_E4M3 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
         return fail(CORR2D_EUNSUPPORTED, "FP8 e4m3 requires per-band scaling (range 448)");
     if (d->tile < 0 || d->tile > 3)
@@ -325,6 +326,7 @@ PrepJob make_prep_job(const corr2d_plan_s* p, const Geo& g, const SetLayout& s, 
     j.B0 = s.has_b ? at<char>(ws, s.B0) : nullptr;
     j.B1 = (s.has_b && s.B1) ? at<char>(ws, s.B1) : nullptr;
     j.alpha = p->d.scale_alpha;
+    j.hilbert = p->d.hilbert;
     return j;
 }
 
@@ -336,14 +338,38 @@ int transform_blocks(const Geo& g, int prec) {
     return (int)((g.n_pad / 64) * ((g.rows_pad + 255) / 256));
 }
 
-// Tiles of the upper triangle when a row tile is R column tiles tall: row
-// tile I pairs with column tiles J >= R I of the R T column tiles.
+// The radix FFT transform serves the Fourier basis for power-of-two m in
+// [128, 1024] in the reduced precisions; FP64 keeps the FP64 MFMA product,
+// and a flag asks for the product everywhere.
+bool use_fft(const corr2d_desc* d, int64_t m) {
+    if (d->flags & CORR2D_FLAG_TRANSFORM_MATMUL) return false;
+    if (d->basis != CORR2D_BASIS_FOURIER || d->prec == CORR2D_PREC_F64) return false;
+    return m >= 128 && m <= 1024 && (m & (m - 1)) == 0;
+}
+int fft_log2(int64_t m) {
+    int l = 0;
+    while (((int64_t)1 << l) < 2 * m) ++l;
+    return l;
+}
+int fft_blocks(const Geo& g) { return (int)(g.n_pad / kFftPoints); }
+
 // The Q N rows of the table (Fourier basis, Noda's kernel) come from their
 // own kernel.
 bool needs_qn(const corr2d_plan_s* p) {
     return p->d.basis == CORR2D_BASIS_FOURIER && p->d.hilbert == CORR2D_HILBERT_NODA;
 }
 
+// Tables of a single or heterocorrelation plan: the DFT table (and its Q N
+// rows), or the twiddles and Noda multiplier of the radix FFT transform.
+hipError_t launch_prep_tables(const corr2d_plan_s* p, const TableSrcInline& ts, hipStream_t s) {
+    if (p->fft) return launch_fft_tables(ts, p->g1.m, s);
+    hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
+    if (e == hipSuccess && needs_qn(p)) e = launch_tables_qn(ts, qn_blocks(p->g1.m), p->g1.m, s);
+    return e;
+}
+
+// Tiles of the upper triangle when a row tile is R column tiles tall: row
+// tile I pairs with column tiles J >= R I of the R T column tiles.
 int64_t triangle_tiles(int64_t T, int64_t R) { return R * T * (T + 1) / 2; }
 
 CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1, const Geo& g2,
@@ -465,6 +491,7 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     }
     const bool t64 = d->prec == CORR2D_PREC_F64;
     p->g1 = geometry(d->m, d->n1, d->prec);
+    p->fft = use_fft(d, d->m);
     size_t off = 0;
     p->table_off = off;
     off = align256(off + table_bytes(p->g1, t64));
@@ -642,6 +669,7 @@ corr2d_status corr2d_plan_get_info(corr2d_plan_t p, corr2d_plan_info* info) {
         info->n_pad = p->g1.n_pad;
         info->tiles = p->ntiles;
         info->c = p->c;
+        info->transform = p->fft ? 1 : 0;
     }
     return ok();
 }
@@ -708,8 +736,7 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
-    hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
-    if (e == hipSuccess && needs_qn(p)) e = launch_tables_qn(ts, qn_blocks(p->g1.m), p->g1.m, s);
+    hipError_t e = launch_prep_tables(p, ts, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     const void* yc = y;
@@ -728,8 +755,13 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     ps.blocks0 = center_blocks(p->g1);
     e = launch_center(ps, ps.blocks0, s);
     if (e != hipSuccess) return device_fail(e, "center launch");
-    ps.blocks0 = transform_blocks(p->g1, p->d.prec);
-    e = launch_transform(p->d.prec, ps, ps.blocks0, s);
+    if (p->fft) {
+        ps.blocks0 = fft_blocks(p->g1);
+        e = launch_fft_transform(p->d.prec, fft_log2(p->g1.m), ps, ps.blocks0, s);
+    } else {
+        ps.blocks0 = transform_blocks(p->g1, p->d.prec);
+        e = launch_transform(p->d.prec, ps, ps.blocks0, s);
+    }
     if (e != hipSuccess) return device_fail(e, "transform launch");
 
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g1, p->s1, ws, phi, psi, true, p->c, p->tile,
@@ -760,8 +792,7 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
-    hipError_t e = launch_tables(ts, ts.blocks0, p->g1.m, s);
-    if (e == hipSuccess && needs_qn(p)) e = launch_tables_qn(ts, qn_blocks(p->g1.m), p->g1.m, s);
+    hipError_t e = launch_prep_tables(p, ts, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     const void *yc1 = y1, *yc2 = y2;
@@ -784,8 +815,13 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     ps.blocks0 = center_blocks(p->g1);
     e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
     if (e != hipSuccess) return device_fail(e, "center launch");
-    ps.blocks0 = transform_blocks(p->g1, p->d.prec);
-    e = launch_transform(p->d.prec, ps, ps.blocks0 + transform_blocks(p->g2, p->d.prec), s);
+    if (p->fft) {
+        ps.blocks0 = fft_blocks(p->g1);
+        e = launch_fft_transform(p->d.prec, fft_log2(p->g1.m), ps, ps.blocks0 + fft_blocks(p->g2), s);
+    } else {
+        ps.blocks0 = transform_blocks(p->g1, p->d.prec);
+        e = launch_transform(p->d.prec, ps, ps.blocks0 + transform_blocks(p->g2, p->d.prec), s);
+    }
     if (e != hipSuccess) return device_fail(e, "transform launch");
 
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g2, p->s2, ws, phi, psi, false, p->c, p->tile,

@@ -660,6 +660,338 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
 }
 
 // =========================================================================
+// Radix FFT transform (power-of-two m, Fourier basis, FP32)
+// =========================================================================
+// For m = 2^s, 128 <= m <= 1024, the perturbation-axis transform runs as
+// FFTs of length L = 2m in LDS instead of the product with the table (m^2
+// work per spectral point becomes m log m).  Two spectral points y1, y2
+// travel as one complex sequence z = y1 + i y2, zero padded to L:
+//   Z = FFT_L(z).  Its even bins are the m-point spectra of the pair,
+//       Y1(p) = (Z(2p) + conj Z(L-2p)) / 2 and Y2(p) = (Z(2p) - conj Z(L-2p)) / 2i
+//       (Eq. (disFT)), packed into A's rows as the table's rows pack them.
+//   Noda's kernel (Eq. (HilbNoda)): (N y)_j = sum_d h(d) y_(j+d) with
+//       h(d) = 1/(pi d), d != 0, is a linear correlation; the zero padding
+//       makes the circular correlation of length L equal to it on j < m, so
+//       r = N z = IFFT_L(Z . i G) with G(w) = (2/L) sum_{d=1}^{m-1} h(d)
+//       sin(2 pi w d / L) (the DFT of h is -2i sum h(d) sin(...)).  B's rows
+//       are the packed m-point spectra of r1 + i r2 = r, taken as the even
+//       bins of the FFT_L of r with its entries from m on set to zero.  The
+//       inverse runs as a forward FFT between conjugations.
+//   Circular kernel (and the R code's bin list): B's rows are those of
+//       i Y (each (Re, Im) pair becomes (-Im, Re)), DC and Nyquist zero.
+// Each pair is transformed by G = L/8 threads holding 8 values each; a pass
+// of radix R (8, then 4 or 2 for the last) is a Stockham step in place of
+// the usual bit reversal, so every FFT leaves its output in natural order.
+// Two LDS buffers per pair alternate between passes (one barrier per pass).
+// LDS indices are padded by one entry in 16 against bank conflicts.
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
+__device__ inline int fpad(int i) { return i + (i >> 4); }
+
+// In-register forward DFTs (exp(-2 pi i j k / R)) of v[O .. O+R-1], outputs
+// in natural order.
+template <int O>
+__device__ inline void dft2(float2 (&v)[8]) {
+    const float2 a = v[O];
+    v[O] = cadd(a, v[O + 1]);
+    v[O + 1] = csub(a, v[O + 1]);
+}
+template <int O, int S = 1>
+__device__ inline void dft4(float2 (&v)[8]) {
+    const float2 a0 = cadd(v[O], v[O + 2 * S]), a1 = csub(v[O], v[O + 2 * S]);
+    const float2 a2 = cadd(v[O + S], v[O + 3 * S]), a3 = mul_mi(csub(v[O + S], v[O + 3 * S]));
+    v[O] = cadd(a0, a2);
+    v[O + 2 * S] = csub(a0, a2);
+    v[O + S] = cadd(a1, a3);
+    v[O + 3 * S] = csub(a1, a3);
+}
+__device__ inline void dft8(float2 (&v)[8]) {
+    constexpr float r = 0.70710678118654752f;
+    // E = DFT4 of the even inputs, O = DFT4 of the odd ones (in place, stride 2)
+    dft4<0, 2>(v);
+    dft4<1, 2>(v);
+    // X_k = E_k + W^k O_k, X_(k+4) = E_k - W^k O_k, W = exp(-i pi / 4)
+    const float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    const float2 o0 = v[1];
+    const float2 o1 = make_float2(r * (v[3].x + v[3].y), r * (v[3].y - v[3].x));
+    const float2 o2 = mul_mi(v[5]);
+    const float2 o3 = make_float2(r * (v[7].y - v[7].x), -r * (v[7].x + v[7].y));
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+template <int L> struct FftCfg {
+    static constexpr int G = L / 8;              // threads per pair
+    static constexpr int PW = 256 / G;           // pairs per pass of the workgroup
+    static constexpr int BUF = L + L / 16;       // padded entries of one buffer
+    static constexpr int PTS = kFftPoints;       // spectral points per workgroup
+    static constexpr int ITER = PTS / (2 * PW);
+    static_assert(ITER >= 1 && PTS % (2 * PW) == 0, "workgroup shape");
+};
+
+// One Stockham pass of radix R at stride NS: butterfly j (this thread's
+// j = t + b G, b < 8/R) takes inputs j + r L/R (held in v), applies the
+// twiddles exp(-2 pi i r (j mod NS) / (NS R)), transforms, and writes output
+// r to (j div NS) NS R + (j mod NS) + r NS.
+template <int L, int R, int NS>
+__device__ inline void fft_pass(float2 (&v)[8], float2* dst, const float2* tw, int t) {
+    constexpr int G = L / 8, NB = 8 / R, STEP = L / (NS * R);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * G, k = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[r * k * STEP]);
+        }
+        if constexpr (R == 8) dft8(v);
+        else if constexpr (R == 4) { if (b == 0) dft4<0>(v); else dft4<4>(v); }
+        else {
+            if (b == 0) dft2<0>(v);
+            else if (b == 1) dft2<2>(v);
+            else if (b == 2) dft2<4>(v);
+            else dft2<6>(v);
+        }
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[fpad(base + r * NS)] = v[b * R + r];
+    }
+}
+
+template <int L, int R>
+__device__ inline void fft_load(float2 (&v)[8], const float2* src, int t) {
+    constexpr int G = L / 8, NB = 8 / R;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b * R + r] = src[fpad(t + b * G + r * (L / R))];
+}
+
+// Forward FFT of the pair whose first-pass inputs v[r] = z(t + r G) this
+// thread holds.  Passes write base + off and base + (off ^ BUF) in turn;
+// returns the offset of the buffer holding the natural-order output (after
+// a workgroup barrier).
+template <int L, int NS = 1>
+__device__ inline int fft_run(float2 (&v)[8], float2* base, int off, const float2* tw, int t) {
+    constexpr int R = (L / NS) >= 8 ? 8 : L / NS;
+    fft_pass<L, R, NS>(v, base + off, tw, t);
+    __syncthreads();
+    if constexpr (NS * R < L) {
+        constexpr int R2 = (L / (NS * R)) >= 8 ? 8 : L / (NS * R);
+        fft_load<L, R2>(v, base + off, t);
+        return fft_run<L, NS * R>(v, base, off ^ FftCfg<L>::BUF, tw, t);
+    } else {
+        return off;
+    }
+}
+
+// Rows k0 .. k0+7 (k0 a multiple of 8) of the packed half spectrum of one
+// point of a pair, from the pair's natural-order L-point spectrum Z: row 0
+// is Re Y(0), rows 2p-1, 2p are sqrt2 Re Y(p), sqrt2 Im Y(p), row m-1 is
+// Re Y(m/2).  rot: rows of i Y with DC and Nyquist zero; zero_nyq: the
+// Nyquist row is zero.
+template <int L>
+__device__ inline void packed_rows8(const float2* Z, bool second, int k0, bool rot, bool zero_nyq,
+                                    float (&x)[8]) {
+    constexpr int M = L / 2;
+    constexpr float hf = 0.5f, s2 = 0.70710678118654752f;
+    float yr[5], yi[5];   // 2 Re Y(p), 2 Im Y(p) for p = k0/2 .. k0/2 + 4
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int p = (k0 >> 1) + q;
+        const float2 a = Z[fpad(2 * p)], b = Z[fpad((L - 2 * p) & (L - 1))];
+        yr[q] = second ? a.y + b.y : a.x + b.x;
+        yi[q] = second ? b.x - a.x : a.y - b.y;
+    }
+    if (!rot) {
+        x[0] = k0 == 0 ? hf * yr[0] : s2 * yi[0];
+        x[1] = s2 * yr[1];
+        x[2] = s2 * yi[1];
+        x[3] = s2 * yr[2];
+        x[4] = s2 * yi[2];
+        x[5] = s2 * yr[3];
+        x[6] = s2 * yi[3];
+        x[7] = k0 + 7 == M - 1 ? (zero_nyq ? 0.0f : hf * yr[4]) : s2 * yr[4];
+    } else {
+        x[0] = k0 == 0 ? 0.0f : s2 * yr[0];
+        x[1] = -s2 * yi[1];
+        x[2] = s2 * yr[1];
+        x[3] = -s2 * yi[2];
+        x[4] = s2 * yr[2];
+        x[5] = -s2 * yi[3];
+        x[6] = s2 * yr[3];
+        x[7] = k0 + 7 == M - 1 ? 0.0f : -s2 * yi[4];
+    }
+}
+
+// Eight consecutive contraction elements of one operand row (idx a multiple
+// of 8) rounded to the operand format, one vector store per plane.
+template <int P>
+__device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const float (&x)[8]) {
+    if constexpr (P == P_F32) {
+        float4* d = (float4*)((float*)p0 + idx);
+        d[0] = make_float4(x[0], x[1], x[2], x[3]);
+        d[1] = make_float4(x[4], x[5], x[6], x[7]);
+    } else if constexpr (P == P_SPLIT || P == P_BF16) {
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint16_t h0 = bf16_rne(x[2 * q]), h1 = bf16_rne(x[2 * q + 1]);
+            hw[q] = h0 | ((uint32_t)h1 << 16);
+            lw[q] = bf16_rne(x[2 * q] - bf16_val(h0)) | ((uint32_t)bf16_rne(x[2 * q + 1] - bf16_val(h1)) << 16);
+        }
+        *(uint4*)((uint16_t*)p0 + idx) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        if constexpr (P == P_SPLIT) *(uint4*)((uint16_t*)p1 + idx) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    } else if constexpr (P == P_F16) {
+        *(h8*)((_Float16*)p0 + idx) = h8{(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3],
+                                         (_Float16)x[4], (_Float16)x[5], (_Float16)x[6], (_Float16)x[7]};
+    } else if constexpr (P == P_FP8) {
+        uint32_t w[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            w[q] = fp8_e4m3_rne(x[4 * q]) | ((uint32_t)fp8_e4m3_rne(x[4 * q + 1]) << 8) |
+                   ((uint32_t)fp8_e4m3_rne(x[4 * q + 2]) << 16) | ((uint32_t)fp8_e4m3_rne(x[4 * q + 3]) << 24);
+        *(uint2*)((uint8_t*)p0 + idx) = make_uint2(w[0], w[1]);
+    }
+}
+
+// One operand's rows for the 2 PW points of a pass: 256 tasks of 8 rows.
+// Blocked layout: lanes in pairs cover the two halves of one point's K
+// block, consecutive pairs consecutive points (one contiguous run per
+// block); row layout: consecutive lanes cover consecutive rows of a point.
+template <int P, int L>
+__device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs, int off, int tid,
+                                bool isB, bool rot, bool zero_nyq, const float* s_sc, int pt0) {
+    constexpr int M = L / 2, NP = 2 * FftCfg<L>::PW;
+    int pt, hb;
+    if constexpr (blocked_layout(P)) {
+        const int u = tid >> 1;
+        pt = u % NP;
+        hb = 2 * (u / NP) + (tid & 1);
+    } else {
+        pt = tid / (M / 8);
+        hb = tid % (M / 8);
+    }
+    const float2* Z = bufs + (pt >> 1) * 2 * FftCfg<L>::BUF + off;
+    float x[8];
+    packed_rows8<L>(Z, pt & 1, 8 * hb, rot, zero_nyq, x);
+    const float sc = s_sc[(isB ? FftCfg<L>::PTS : 0) + pt0 + pt];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] *= sc;
+    const int64_t i = i0 + pt, k = 8 * hb;
+    const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
+    store_operand8<P>(isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx, x);
+}
+
+template <int P, int LOG2L, class Src>
+__global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
+    static_assert(P != P_F64, "the FP64 path keeps the transform GEMM");
+    constexpr int L = 1 << LOG2L;
+    using C = FftCfg<L>;
+    __shared__ float2 s_buf[C::PW * 2 * C::BUF];
+    __shared__ float2 s_tw[L];
+    __shared__ float s_g[L];
+    __shared__ float s_sc[2 * C::PTS];
+    int lb;
+    const PrepJob J = src.get(blockIdx.x, lb);
+    const int tid = threadIdx.x, grp = tid / C::G, t = tid % C::G;
+    const bool noda = J.need_b && J.hilbert == H_NODA;
+    const bool rcompat = J.hilbert == H_R_COMPAT;
+    const int64_t p0 = (int64_t)lb * C::PTS;   // first spectral point of the workgroup
+    const float2* tab = (const float2*)J.table;
+    for (int e = tid; e < L; e += 256) {
+        s_tw[e] = tab[e];
+        s_g[e] = noda ? ((const float*)(tab + L))[e] : 0.0f;
+    }
+    if (tid < 2 * C::PTS) {
+        const float* sp = tid < C::PTS ? J.sA : J.sB;
+        s_sc[tid] = sp != nullptr ? sp[p0 + (tid % C::PTS)] : 0.0f;
+    }
+    __syncthreads();
+    const float* Y = (const float*)J.yt;
+    float2* mine = s_buf + grp * 2 * C::BUF;
+    int off = 0;   // buffer holding the last FFT output (all pairs alike)
+#pragma unroll 1
+    for (int it = 0; it < C::ITER; ++it) {
+        const int pt0 = it * 2 * C::PW;
+        const int64_t i0 = p0 + pt0;
+        const float* y1 = Y + (i0 + 2 * grp) * J.kt;
+        float2 v[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = make_float2(y1[t + r * C::G], y1[J.kt + t + r * C::G]);
+#pragma unroll
+        for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
+        off = fft_run<L>(v, mine, off ^ C::BUF, s_tw, t);
+        fft_emit<P, L>(J, i0, s_buf, off, tid, false, false, rcompat, s_sc, pt0);
+        if (J.need_b && !noda) fft_emit<P, L>(J, i0, s_buf, off, tid, true, true, false, s_sc, pt0);
+        if (noda) {
+            // conj(i G Z): the inverse transform as a forward one
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int w = t + r * C::G;
+                const float2 z = mine[off + fpad(w)];
+                const float g = s_g[w];
+                v[r] = make_float2(-g * z.y, -g * z.x);
+            }
+            off = fft_run<L>(v, mine, off ^ C::BUF, s_tw, t);
+            // r = conj of that, entries from m on dropped
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 u = mine[off + fpad(t + r * C::G)];
+                v[r] = make_float2(u.x, -u.y);
+            }
+#pragma unroll
+            for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
+            off = fft_run<L>(v, mine, off ^ C::BUF, s_tw, t);
+            fft_emit<P, L>(J, i0, s_buf, off, tid, true, false, false, s_sc, pt0);
+        }
+    }
+}
+
+// Tables of the radix FFT transform, L = 2m: tw[w] = exp(-2 pi i w / L) and,
+// for Noda's kernel, g[w] = (2/L) sum_{d=1}^{m-1} sin(2 pi w d / L) / (pi d)
+// (FP64 sums, stored as float; g follows the L twiddles).  One workgroup
+// per w.
+template <class Src>
+__global__ __launch_bounds__(256) void fft_tables_kernel(Src src) {
+    __shared__ double part[256];
+    int w;
+    const TableJob T = src.get_q(blockIdx.x, w);
+    const int64_t m = T.m, L = 2 * m;
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    if (T.hilbert == H_NODA) {
+        for (int64_t d = tid + 1; d < m; d += 256) {
+            double sv, cv;
+            sincospi(2.0 * (double)(((int64_t)w * d) % L) / (double)L, &sv, &cv);
+            s += sv / (M_PI * (double)d);
+        }
+    }
+    part[tid] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) part[tid] += part[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double sv, cv;
+        sincospi(2.0 * (double)w / (double)L, &sv, &cv);
+        float2* tw = (float2*)T.table;
+        tw[w] = make_float2((float)cv, (float)-sv);
+        ((float*)(tw + L))[w] = (float)(2.0 * part[0] / (double)L);
+    }
+}
+
+// =========================================================================
 // Correlation GEMM
 // =========================================================================
 template <int P> struct Frag;
@@ -1512,6 +1844,34 @@ static hipError_t launch_transform_t(int prec, const Src& src, int blocks, hipSt
 }
 hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s) {
     return launch_transform_t(prec, src, blocks, s);
+}
+
+hipError_t launch_fft_tables(const TableSrcInline& src, int64_t m, hipStream_t s) {
+    hipLaunchKernelGGL(fft_tables_kernel<TableSrcInline>, dim3((unsigned)(2 * m)), dim3(256), 0, s, src);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_fft_p(int log2l, const PrepSrcInline& src, int blocks, hipStream_t s) {
+    switch (log2l) {
+    case 8: hipLaunchKernelGGL((fft_transform_kernel<P, 8, PrepSrcInline>), dim3(blocks), dim3(256), 0, s, src); break;
+    case 9: hipLaunchKernelGGL((fft_transform_kernel<P, 9, PrepSrcInline>), dim3(blocks), dim3(256), 0, s, src); break;
+    case 10: hipLaunchKernelGGL((fft_transform_kernel<P, 10, PrepSrcInline>), dim3(blocks), dim3(256), 0, s, src); break;
+    case 11: hipLaunchKernelGGL((fft_transform_kernel<P, 11, PrepSrcInline>), dim3(blocks), dim3(256), 0, s, src); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_transform(int prec, int log2l, const PrepSrcInline& src, int blocks, hipStream_t s) {
+    switch (prec) {
+    case P_F32: return launch_fft_p<P_F32>(log2l, src, blocks, s);
+    case P_SPLIT: return launch_fft_p<P_SPLIT>(log2l, src, blocks, s);
+    case P_BF16: return launch_fft_p<P_BF16>(log2l, src, blocks, s);
+    case P_F16: return launch_fft_p<P_F16>(log2l, src, blocks, s);
+    case P_FP8: return launch_fft_p<P_FP8>(log2l, src, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s) {
     return launch_transform_t(prec, src, blocks, s);

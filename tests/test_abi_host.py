@@ -124,6 +124,8 @@ def _plan_status(**kw):
     (dict(out_layout=2), B.OK),
     (dict(prec=5, flags=B.FLAG_NO_PER_BAND_SCALE), B.EUNSUPPORTED),
     (dict(flags=0x100), B.EINVAL),
+    (dict(flags=0x20), B.EINVAL),
+    (dict(flags=B.FLAG_TRANSFORM_MATMUL), B.OK),
     (dict(tile=7), B.EINVAL),
     (dict(prec=0, tile=2), B.EUNSUPPORTED),
     (dict(prec=1, tile=3), B.EUNSUPPORTED),
@@ -189,6 +191,24 @@ def test_plan_info():
     _, h = B.corr2d_plan(d)
     import math
     assert B.corr2d_plan_get_info(h).c == pytest.approx(10 / (math.pi * 9))
+    B.corr2d_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw,fft", [
+    (dict(m=256), 1), (dict(m=128), 1), (dict(m=512), 1), (dict(m=1024), 1),
+    (dict(m=64), 0), (dict(m=127), 0), (dict(m=384), 0), (dict(m=2048), 0),
+    (dict(m=256, prec="f64"), 0), (dict(m=256, basis="time"), 0),
+    (dict(m=256, flags=B.FLAG_TRANSFORM_MATMUL), 0),
+    (dict(m=256, hilbert="circular"), 1), (dict(m=256, hilbert="r_compat"), 1),
+    (dict(m=128, n2=40), 1), (dict(m=256, prec="fp8_e4m3"), 1),
+])
+def test_transform_selection(kw, fft):
+    """The radix FFT transform serves the Fourier basis for power-of-two
+    128 <= m <= 1024 outside FP64, unless the flag asks for the product."""
+    base = dict(n1=300)
+    base.update(kw)
+    _, h = B.corr2d_plan(B.corr2d_desc_init(**base))
+    assert B.corr2d_plan_get_info(h).transform == fft
     B.corr2d_plan_destroy(h)
 
 

@@ -466,6 +466,72 @@ def test_interpolation_hetero_f32_input_scaled(gpu):
 
 
 # --------------------------------------------------------------------------
+# Radix FFT transform (power-of-two 128 <= m <= 1024, Fourier basis)
+# --------------------------------------------------------------------------
+FFT_PRECS = ["f32", "split_bf16", "bf16", "f16", "fp8_e4m3"]
+
+
+def _transform(plan):
+    return B.corr2d_plan_get_info(plan.handle).transform
+
+
+@pytest.mark.parametrize("prec", FFT_PRECS)
+@pytest.mark.parametrize("m,n", [(128, 300), (256, 129), (512, 70), (1024, 33)])
+def test_fft_transform_parity(gpu, prec, m, n):
+    """Every FFT length (L = 256 .. 2048: radix 8 passes with a radix-4 or
+    radix-2 last pass) and operand format; ragged n leaves padded points."""
+    S = _rand(m, n, 31 * m + n)
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, plan = _homo(S, gpu, prec=prec)
+    assert _transform(plan) == 1
+    check_homo_structure(phi, psi)
+    assert rel_fro(phi, phi_o) <= TOL[prec]
+    assert rel_fro(psi, psi_o) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "split_bf16"])
+@pytest.mark.parametrize("hilbert,norm", [("noda", "noda"), ("circular", "noda"), ("r_compat", "paper")])
+def test_fft_transform_modes_and_matmul_flag(gpu, prec, hilbert, norm):
+    """Each asynchronous kernel through the FFT transform against the oracle;
+    the same plan forced onto the table product agrees with both."""
+    m, n = 256, 200
+    S = _rand(m, n, 77)
+    phi_o, psi_o = oracle.corr2d(S, hilbert=hilbert, norm=norm)
+    a = _homo(S, gpu, prec=prec, hilbert=hilbert, norm=norm)
+    b = _homo(S, gpu, prec=prec, hilbert=hilbert, norm=norm, flags=B.FLAG_TRANSFORM_MATMUL)
+    assert _transform(a[2]) == 1 and _transform(b[2]) == 0
+    for phi, psi, _ in (a, b):
+        check_homo_structure(phi, psi)
+        assert rel_fro(phi, phi_o) <= TOL[prec]
+        assert rel_fro(psi, psi_o) <= TOL[prec]
+    assert rel_fro(a[0], b[0]) <= TOL[prec] and rel_fro(a[1], b[1]) <= TOL[prec]
+
+
+def test_fft_transform_hetero_ref_scaled(gpu):
+    """Heterocorrelation (the left set needs no B operand), a user reference
+    on one side and Pareto scaling through the FFT transform."""
+    m, n1, n2 = 128, 150, 90
+    S1, S2 = _rand(m, n1, 600), _rand(m, n2, 601) * 5.0
+    r1 = S1[7] - 0.2
+    phi_o, psi_o = oracle.corr2d(S1, S2, ref1=r1, alpha=0.5)
+    phi, psi, plan, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), ref1=_t(r1, gpu), prec="split_bf16",
+                                 alpha=0.5)
+    assert _transform(plan) == 1
+    assert rel_fro(_np(phi), phi_o) <= TOL["split_bf16"]
+    assert rel_fro(_np(psi), psi_o) <= TOL["split_bf16"]
+
+
+def test_fft_transform_after_interpolation(gpu):
+    m_in, m_out, n = 90, 128, 140
+    t = _uneven(m_in, 610)
+    S = _rand(m_in, n, 611)
+    phi_o, psi_o = oracle.corr2d(oracle.interpolate(S, t, m_out, "spline"))
+    phi, psi, plan = _homo(S, gpu, prec="f32", interp="spline", t_in=t, m_out=m_out)
+    assert _transform(plan) == 1
+    assert rel_fro(phi, phi_o) <= TOL["f32"] and rel_fro(psi, psi_o) <= TOL["f32"]
+
+
+# --------------------------------------------------------------------------
 # Edge sizes: long perturbation axes (centring without the register cache,
 # the largest m), and a very wide heterocorrelation
 # --------------------------------------------------------------------------
