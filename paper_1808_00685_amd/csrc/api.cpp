@@ -327,6 +327,7 @@ PrepJob make_prep_job(const corr2d_plan_s* p, const Geo& g, const SetLayout& s, 
     j.B1 = (s.has_b && s.B1) ? at<char>(ws, s.B1) : nullptr;
     j.alpha = p->d.scale_alpha;
     j.hilbert = p->d.hilbert;
+    j.basis = p->d.basis;
     return j;
 }
 
@@ -338,12 +339,13 @@ int transform_blocks(const Geo& g, int prec) {
     return (int)((g.n_pad / 64) * ((g.rows_pad + 255) / 256));
 }
 
-// The radix FFT transform serves the Fourier basis for power-of-two m in
-// [128, 1024] in the reduced precisions; FP64 keeps the FP64 MFMA product,
-// and a flag asks for the product everywhere.
+// The radix FFT transform serves power-of-two m in [128, 1024] in the
+// reduced precisions: the Fourier basis, and the time basis with Noda's
+// kernel (B = N Yc as an FFT correlation).  FP64 keeps the FP64 MFMA
+// product, and a flag asks for the product everywhere.
 bool use_fft(const corr2d_desc* d, int64_t m) {
-    if (d->flags & CORR2D_FLAG_TRANSFORM_MATMUL) return false;
-    if (d->basis != CORR2D_BASIS_FOURIER || d->prec == CORR2D_PREC_F64) return false;
+    if (d->flags & CORR2D_FLAG_TRANSFORM_MATMUL || d->prec == CORR2D_PREC_F64) return false;
+    if (d->basis == CORR2D_BASIS_TIME && d->hilbert != CORR2D_HILBERT_NODA) return false;
     return m >= 128 && m <= 1024 && (m & (m - 1)) == 0;
 }
 int fft_log2(int64_t m) {
@@ -351,7 +353,7 @@ int fft_log2(int64_t m) {
     while (((int64_t)1 << l) < 2 * m) ++l;
     return l;
 }
-int fft_blocks(const Geo& g) { return (int)(g.n_pad / kFftPoints); }
+int fft_blocks(const Geo& g) { return (int)(g.n_pad / fft_points((int)(2 * g.m))); }
 
 // The Q N rows of the table (Fourier basis, Noda's kernel) come from their
 // own kernel.

@@ -81,8 +81,8 @@ struct PrepJob {
     void* A0; void* A1;   // operand A planes, n_pad x kp (A1: split low plane)
     void* B0; void* B1;   // operand B planes
     double alpha;         // result scaling exponent (0: none): columns x sigma^-alpha
-    int32_t hilbert;      // Hilbert (the radix FFT transform builds B itself)
-    int32_t pad1;
+    int32_t hilbert;      // Hilbert and Basis (the radix FFT transform builds
+    int32_t basis;        // the operands from them, without a table)
 };
 
 // Resampling of one data set onto the equidistant perturbation grid: out =

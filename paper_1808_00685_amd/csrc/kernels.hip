@@ -48,14 +48,18 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ rounding
-// float -> bfloat16, round to nearest even (bias-and-truncate on the bits).
-__device__ inline uint16_t bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// Two floats -> a packed pair of bfloat16 (a in the low half), round to
+// nearest even: v_cvt_pk_bf16_f32.
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t bf16x2_rne(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf2v));
 }
-__device__ inline float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// Split of a pair: hi = RNE(x), lo = RNE(x - hi) (x - hi is exact in FP32).
+__device__ inline void bf16x2_split(float a, float b, uint32_t& hi, uint32_t& lo) {
+    hi = bf16x2_rne(a, b);
+    lo = bf16x2_rne(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
 
 // float -> OCP FP8 e4m3 (bias 7, 3 mantissa bits, largest finite 448, no
 // infinities), round to nearest even, saturating at +-448; NaN -> 0x7f.
@@ -483,15 +487,11 @@ __device__ inline void store_operand4(void* p0, void* p1, int64_t idx, const flo
     if constexpr (P == P_F32) {
         *(float4*)((float*)p0 + idx) = make_float4(x[0], x[1], x[2], x[3]);
     } else if constexpr (P == P_SPLIT || P == P_BF16) {
-        uint16_t hi[4], lo[4];
+        uint32_t hw[2], lw[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            hi[q] = bf16_rne(x[q]);
-            lo[q] = bf16_rne(x[q] - bf16_val(hi[q]));
-        }
-        *(uint2*)((uint16_t*)p0 + idx) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
-        if constexpr (P == P_SPLIT)
-            *(uint2*)((uint16_t*)p1 + idx) = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+        for (int q = 0; q < 2; ++q) bf16x2_split(x[2 * q], x[2 * q + 1], hw[q], lw[q]);
+        *(uint2*)((uint16_t*)p0 + idx) = make_uint2(hw[0], hw[1]);
+        if constexpr (P == P_SPLIT) *(uint2*)((uint16_t*)p1 + idx) = make_uint2(lw[0], lw[1]);
     } else if constexpr (P == P_F16) {
         typedef _Float16 h4v __attribute__((ext_vector_type(4)));
         *(h4v*)((_Float16*)p0 + idx) = h4v{(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3]};
@@ -679,11 +679,14 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
 //       inverse runs as a forward FFT between conjugations.
 //   Circular kernel (and the R code's bin list): B's rows are those of
 //       i Y (each (Re, Im) pair becomes (-Im, Re)), DC and Nyquist zero.
+//   Time basis (Noda's kernel): A is the centred spectrum itself and B is r.
 // Each pair is transformed by G = L/8 threads holding 8 values each; a pass
 // of radix R (8, then 4 or 2 for the last) is a Stockham step in place of
 // the usual bit reversal, so every FFT leaves its output in natural order.
 // Two LDS buffers per pair alternate between passes (one barrier per pass).
-// LDS indices are padded by one entry in 16 against bank conflicts.
+// LDS indices are padded by one entry in 16 against bank conflicts.  The
+// twiddles of each pass and the Noda multiplier depend only on the thread's
+// index within its pair, so each thread keeps its own in registers.
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ inline float2 cmul(float2 a, float2 b) {
@@ -730,30 +733,70 @@ __device__ inline void dft8(float2 (&v)[8]) {
     v[7] = csub(e3, o3);
 }
 
+// dft8 of inputs whose last four are zero (the zero-padded half of a
+// first pass).
+__device__ inline void dft8_half(float2 (&v)[8]) {
+    constexpr float r = 0.70710678118654752f;
+    const float2 e0 = cadd(v[0], v[2]), e2 = csub(v[0], v[2]);
+    const float2 e1 = cadd(v[0], mul_mi(v[2])), e3 = csub(v[0], mul_mi(v[2]));
+    const float2 q0 = cadd(v[1], v[3]), q2 = csub(v[1], v[3]);
+    const float2 q1 = cadd(v[1], mul_mi(v[3])), q3 = csub(v[1], mul_mi(v[3]));
+    const float2 o1 = make_float2(r * (q1.x + q1.y), r * (q1.y - q1.x));
+    const float2 o2 = mul_mi(q2);
+    const float2 o3 = make_float2(r * (q3.y - q3.x), -r * (q3.x + q3.y));
+    v[0] = cadd(e0, q0);
+    v[4] = csub(e0, q0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
 template <int L> struct FftCfg {
     static constexpr int G = L / 8;              // threads per pair
     static constexpr int PW = 256 / G;           // pairs per pass of the workgroup
     static constexpr int BUF = L + L / 16;       // padded entries of one buffer
-    static constexpr int PTS = kFftPoints;       // spectral points per workgroup
+    static constexpr int PAIR = 2 * BUF + 4;     // LDS entries per pair (staggered banks)
+    static constexpr int PTS = fft_points(L);    // spectral points per workgroup
     static constexpr int ITER = PTS / (2 * PW);
+    static constexpr int NPASS = (__builtin_ctz(L) + 2) / 3;
     static_assert(ITER >= 1 && PTS % (2 * PW) == 0, "workgroup shape");
 };
+
+// This thread's twiddles: pass q (stride NS, radix R) multiplies input r of
+// its butterfly b by exp(-2 pi i r k / (NS R)), k = (t + b G) mod NS.
+template <int L> struct FftTw { float2 w[FftCfg<L>::NPASS][8]; };
+
+template <int L, int NS = 1, int PASS = 0>
+__device__ inline void fft_twiddles(FftTw<L>& tw, const float2* tab, int t) {
+    constexpr int R = (L / NS) >= 8 ? 8 : L / NS, NB = 8 / R, STEP = L / (NS * R);
+    if constexpr (NS > 1) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 1; r < R; ++r) tw.w[PASS][b * R + r] = tab[r * ((t + b * FftCfg<L>::G) & (NS - 1)) * STEP];
+    }
+    if constexpr (NS * R < L) fft_twiddles<L, NS * R, PASS + 1>(tw, tab, t);
+}
 
 // One Stockham pass of radix R at stride NS: butterfly j (this thread's
 // j = t + b G, b < 8/R) takes inputs j + r L/R (held in v), applies the
 // twiddles exp(-2 pi i r (j mod NS) / (NS R)), transforms, and writes output
 // r to (j div NS) NS R + (j mod NS) + r NS.
-template <int L, int R, int NS>
-__device__ inline void fft_pass(float2 (&v)[8], float2* dst, const float2* tw, int t) {
-    constexpr int G = L / 8, NB = 8 / R, STEP = L / (NS * R);
+template <int L, int R, int NS, bool HALF>
+__device__ inline void fft_pass(float2 (&v)[8], float2* dst, const float2 (&tw)[8], int t) {
+    constexpr int G = L / 8, NB = 8 / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + b * G, k = j & (NS - 1);
         if constexpr (NS > 1) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[r * k * STEP]);
+            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tw[b * R + r]);
         }
-        if constexpr (R == 8) dft8(v);
+        if constexpr (R == 8 && HALF) dft8_half(v);
+        else if constexpr (R == 8) dft8(v);
         else if constexpr (R == 4) { if (b == 0) dft4<0>(v); else dft4<4>(v); }
         else {
             if (b == 0) dft2<0>(v);
@@ -777,18 +820,18 @@ __device__ inline void fft_load(float2 (&v)[8], const float2* src, int t) {
 }
 
 // Forward FFT of the pair whose first-pass inputs v[r] = z(t + r G) this
-// thread holds.  Passes write base + off and base + (off ^ BUF) in turn;
-// returns the offset of the buffer holding the natural-order output (after
-// a workgroup barrier).
-template <int L, int NS = 1>
-__device__ inline int fft_run(float2 (&v)[8], float2* base, int off, const float2* tw, int t) {
+// thread holds (HALF: v[4..7] are zero).  Passes write base + off and
+// base + (off ^ BUF) in turn; returns the offset of the buffer holding the
+// natural-order output (after a workgroup barrier).
+template <int L, bool HALF, int NS = 1, int PASS = 0>
+__device__ inline int fft_run(float2 (&v)[8], float2* base, int off, const FftTw<L>& tw, int t) {
     constexpr int R = (L / NS) >= 8 ? 8 : L / NS;
-    fft_pass<L, R, NS>(v, base + off, tw, t);
+    fft_pass<L, R, NS, HALF && NS == 1>(v, base + off, tw.w[PASS], t);
     __syncthreads();
     if constexpr (NS * R < L) {
         constexpr int R2 = (L / (NS * R)) >= 8 ? 8 : L / (NS * R);
         fft_load<L, R2>(v, base + off, t);
-        return fft_run<L, NS * R>(v, base, off ^ FftCfg<L>::BUF, tw, t);
+        return fft_run<L, HALF, NS * R, PASS + 1>(v, base, off ^ FftCfg<L>::BUF, tw, t);
     } else {
         return off;
     }
@@ -844,11 +887,7 @@ __device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const flo
     } else if constexpr (P == P_SPLIT || P == P_BF16) {
         uint32_t hw[4], lw[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint16_t h0 = bf16_rne(x[2 * q]), h1 = bf16_rne(x[2 * q + 1]);
-            hw[q] = h0 | ((uint32_t)h1 << 16);
-            lw[q] = bf16_rne(x[2 * q] - bf16_val(h0)) | ((uint32_t)bf16_rne(x[2 * q + 1] - bf16_val(h1)) << 16);
-        }
+        for (int q = 0; q < 4; ++q) bf16x2_split(x[2 * q], x[2 * q + 1], hw[q], lw[q]);
         *(uint4*)((uint16_t*)p0 + idx) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
         if constexpr (P == P_SPLIT) *(uint4*)((uint16_t*)p1 + idx) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
     } else if constexpr (P == P_F16) {
@@ -868,9 +907,11 @@ __device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const flo
 // Blocked layout: lanes in pairs cover the two halves of one point's K
 // block, consecutive pairs consecutive points (one contiguous run per
 // block); row layout: consecutive lanes cover consecutive rows of a point.
+// seq (time basis): the rows are the sequence itself -- A the centred
+// spectrum, B the correlation r = conj(U) held in the pair's buffer.
 template <int P, int L>
 __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs, int off, int tid,
-                                bool isB, bool rot, bool zero_nyq, const float* s_sc, int pt0) {
+                                bool isB, bool rot, bool zero_nyq, bool seq, const float* s_sc, int pt0) {
     constexpr int M = L / 2, NP = 2 * FftCfg<L>::PW;
     int pt, hb;
     if constexpr (blocked_layout(P)) {
@@ -881,9 +922,22 @@ __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs
         pt = tid / (M / 8);
         hb = tid % (M / 8);
     }
-    const float2* Z = bufs + (pt >> 1) * 2 * FftCfg<L>::BUF + off;
+    const float2* Z = bufs + (pt >> 1) * FftCfg<L>::PAIR + off;
     float x[8];
-    packed_rows8<L>(Z, pt & 1, 8 * hb, rot, zero_nyq, x);
+    if (!seq) {
+        packed_rows8<L>(Z, pt & 1, 8 * hb, rot, zero_nyq, x);
+    } else if (isB) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float2 u = Z[fpad(8 * hb + e)];
+            x[e] = (pt & 1) ? -u.y : u.x;
+        }
+    } else {
+        const float4* src = (const float4*)((const float*)J.yt + (i0 + pt) * J.kt + 8 * hb);
+        const float4 a = src[0], b = src[1];
+        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    }
     const float sc = s_sc[(isB ? FftCfg<L>::PTS : 0) + pt0 + pt];
 #pragma unroll
     for (int e = 0; e < 8; ++e) x[e] *= sc;
@@ -897,28 +951,28 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
     static_assert(P != P_F64, "the FP64 path keeps the transform GEMM");
     constexpr int L = 1 << LOG2L;
     using C = FftCfg<L>;
-    __shared__ float2 s_buf[C::PW * 2 * C::BUF];
-    __shared__ float2 s_tw[L];
-    __shared__ float s_g[L];
+    __shared__ float2 s_buf[C::PW * C::PAIR];
     __shared__ float s_sc[2 * C::PTS];
     int lb;
     const PrepJob J = src.get(blockIdx.x, lb);
     const int tid = threadIdx.x, grp = tid / C::G, t = tid % C::G;
     const bool noda = J.need_b && J.hilbert == H_NODA;
     const bool rcompat = J.hilbert == H_R_COMPAT;
+    const bool tbasis = J.basis == B_TIME;   // (Noda's kernel only)
     const int64_t p0 = (int64_t)lb * C::PTS;   // first spectral point of the workgroup
     const float2* tab = (const float2*)J.table;
-    for (int e = tid; e < L; e += 256) {
-        s_tw[e] = tab[e];
-        s_g[e] = noda ? ((const float*)(tab + L))[e] : 0.0f;
-    }
+    FftTw<L> tw;
+    fft_twiddles<L>(tw, tab, t);
+    float gr[8];   // Noda multiplier G(t + r G)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) gr[r] = noda ? ((const float*)(tab + L))[t + r * C::G] : 0.0f;
     if (tid < 2 * C::PTS) {
         const float* sp = tid < C::PTS ? J.sA : J.sB;
         s_sc[tid] = sp != nullptr ? sp[p0 + (tid % C::PTS)] : 0.0f;
     }
     __syncthreads();
     const float* Y = (const float*)J.yt;
-    float2* mine = s_buf + grp * 2 * C::BUF;
+    float2* mine = s_buf + grp * C::PAIR;
     int off = 0;   // buffer holding the last FFT output (all pairs alike)
 #pragma unroll 1
     for (int it = 0; it < C::ITER; ++it) {
@@ -926,33 +980,38 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
         const int64_t i0 = p0 + pt0;
         const float* y1 = Y + (i0 + 2 * grp) * J.kt;
         float2 v[8];
+        if (tbasis) fft_emit<P, L>(J, i0, s_buf, off, tid, false, false, false, true, s_sc, pt0);
+        if (!tbasis || noda) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = make_float2(y1[t + r * C::G], y1[J.kt + t + r * C::G]);
+            for (int r = 0; r < 4; ++r) v[r] = make_float2(y1[t + r * C::G], y1[J.kt + t + r * C::G]);
 #pragma unroll
-        for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
-        off = fft_run<L>(v, mine, off ^ C::BUF, s_tw, t);
-        fft_emit<P, L>(J, i0, s_buf, off, tid, false, false, rcompat, s_sc, pt0);
-        if (J.need_b && !noda) fft_emit<P, L>(J, i0, s_buf, off, tid, true, true, false, s_sc, pt0);
+            for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
+            off = fft_run<L, true>(v, mine, off ^ C::BUF, tw, t);
+        }
+        if (!tbasis) fft_emit<P, L>(J, i0, s_buf, off, tid, false, false, rcompat, false, s_sc, pt0);
+        if (J.need_b && !noda) fft_emit<P, L>(J, i0, s_buf, off, tid, true, true, false, false, s_sc, pt0);
         if (noda) {
             // conj(i G Z): the inverse transform as a forward one
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                const int w = t + r * C::G;
-                const float2 z = mine[off + fpad(w)];
-                const float g = s_g[w];
-                v[r] = make_float2(-g * z.y, -g * z.x);
+                const float2 z = mine[off + fpad(t + r * C::G)];
+                v[r] = make_float2(-gr[r] * z.y, -gr[r] * z.x);
             }
-            off = fft_run<L>(v, mine, off ^ C::BUF, s_tw, t);
-            // r = conj of that, entries from m on dropped
+            off = fft_run<L, false>(v, mine, off ^ C::BUF, tw, t);
+            if (tbasis) {
+                fft_emit<P, L>(J, i0, s_buf, off, tid, true, false, false, true, s_sc, pt0);
+            } else {
+                // r = conj of that, entries from m on dropped
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float2 u = mine[off + fpad(t + r * C::G)];
-                v[r] = make_float2(u.x, -u.y);
+                for (int r = 0; r < 4; ++r) {
+                    const float2 u = mine[off + fpad(t + r * C::G)];
+                    v[r] = make_float2(u.x, -u.y);
+                }
+#pragma unroll
+                for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
+                off = fft_run<L, true>(v, mine, off ^ C::BUF, tw, t);
+                fft_emit<P, L>(J, i0, s_buf, off, tid, true, false, false, false, s_sc, pt0);
             }
-#pragma unroll
-            for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
-            off = fft_run<L>(v, mine, off ^ C::BUF, s_tw, t);
-            fft_emit<P, L>(J, i0, s_buf, off, tid, true, false, false, s_sc, pt0);
         }
     }
 }

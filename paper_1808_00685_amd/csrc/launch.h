@@ -92,11 +92,12 @@ hipError_t launch_center(const PrepSrcArray& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s);
 // Radix FFT transform (power-of-two m, 128 <= m <= 1024, FFT length
-// L = 2^log2l = 2m; 16 spectral points per workgroup) and its tables
-// (2m workgroups).
+// L = 2^log2l = 2m; fft_points(L) spectral points per workgroup: 8, or the
+// 4096/L points of one pass of its 256 threads) and its tables (2m
+// workgroups).
 hipError_t launch_fft_tables(const TableSrcInline& src, int64_t m, hipStream_t s);
 hipError_t launch_fft_transform(int prec, int log2l, const PrepSrcInline& src, int blocks, hipStream_t s);
-constexpr int kFftPoints = 16;
+constexpr int fft_points(int L) { return 4096 / L > 8 ? 4096 / L : 8; }
 hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s);
 hipError_t launch_corr_persistent(int prec, int fm, int fn, bool out_f64, const CorrJob* jobs,
                                   const int64_t* tile_start, int count, int64_t total,

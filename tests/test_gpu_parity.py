@@ -507,6 +507,23 @@ def test_fft_transform_modes_and_matmul_flag(gpu, prec, hilbert, norm):
     assert rel_fro(a[0], b[0]) <= TOL[prec] and rel_fro(a[1], b[1]) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f32", "split_bf16", "bf16"])
+@pytest.mark.parametrize("m,n", [(128, 150), (512, 70)])
+def test_fft_transform_time_basis(gpu, prec, m, n):
+    """Time basis with Noda's kernel: B = N Yc as an FFT correlation."""
+    S = _rand(m, n, 620 + m)
+    phi_o, psi_o = oracle.corr2d(S)
+    a = _homo(S, gpu, prec=prec, basis="time")
+    b = _homo(S, gpu, prec=prec, basis="time", flags=B.FLAG_TRANSFORM_MATMUL)
+    assert _transform(a[2]) == 1 and _transform(b[2]) == 0
+    for phi, psi, _ in (a, b):
+        check_homo_structure(phi, psi)
+        assert rel_fro(phi, phi_o) <= TOL[prec]
+        assert rel_fro(psi, psi_o) <= TOL[prec]
+    if prec != "bf16":
+        assert np.array_equal(a[0], b[0])   # A is the centred spectrum on both paths
+
+
 def test_fft_transform_hetero_ref_scaled(gpu):
     """Heterocorrelation (the left set needs no B operand), a user reference
     on one side and Pareto scaling through the FFT transform."""
