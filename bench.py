@@ -258,8 +258,12 @@ def time_calls(torch, fn, reps, batches=3):
     return best
 
 
-def kernel_ms(B, torch, plan, call, ev, reps=5):
-    """Mean contraction-kernel time (ms) through the library's timing hook."""
+def kernel_ms(B, torch, plan, call, ev, reps=7):
+    """Median contraction-kernel time (ms) of `reps` calls through the
+    library's timing hook.  The median, not the mean: when the host is late
+    to submit the kernel after the event before it, that one interval
+    includes the wait, and a mean over a few calls of a 40 us kernel takes
+    it in whole."""
     evs = ev.create(2 * reps)
     for r in range(reps):
         B.corr2d_plan_set_timing_events(plan.handle, evs[2 * r], evs[2 * r + 1])
@@ -268,7 +272,7 @@ def kernel_ms(B, torch, plan, call, ev, reps=5):
     ms = [ev.elapsed_ms(evs[2 * r], evs[2 * r + 1]) for r in range(reps)]
     B.corr2d_plan_set_timing_events(plan.handle, None, None)
     ev.destroy(evs)
-    return float(np.mean(ms))
+    return float(np.median(ms))
 
 
 def other_workloads(B, torch, oracle, synth, ev, dev):
