@@ -70,7 +70,7 @@ def write_table(lines, path, header):
 
 
 def time_tile(B, torch, prec, m, n, tile, ev, reps=5):
-    """Mean contraction-kernel time (ms) of one homocorrelation plan (row-aligned
+    """Median contraction-kernel time (ms) of one homocorrelation plan (row-aligned
     upper triangle, the benchmark's layout)."""
     import numpy as np
     dev = torch.device("cuda:0")
