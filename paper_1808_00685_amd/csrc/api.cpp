@@ -755,7 +755,8 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     if (p->interp) ps.j[0].in_f64 = 1;
     ps.count = 1;
     ps.blocks0 = center_blocks(p->g1);
-    e = launch_center(ps, ps.blocks0, s);
+    // the FFT transform centres the spectra itself
+    if (!p->fft) e = launch_center(ps, ps.blocks0, s);
     if (e != hipSuccess) return device_fail(e, "center launch");
     if (p->fft) {
         ps.blocks0 = fft_blocks(p->g1);
@@ -815,7 +816,7 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     if (p->interp) ps.j[0].in_f64 = ps.j[1].in_f64 = 1;
     ps.count = 2;
     ps.blocks0 = center_blocks(p->g1);
-    e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
+    if (!p->fft) e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
     if (e != hipSuccess) return device_fail(e, "center launch");
     if (p->fft) {
         ps.blocks0 = fft_blocks(p->g1);

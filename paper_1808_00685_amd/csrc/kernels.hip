@@ -762,8 +762,80 @@ template <int L> struct FftCfg {
     static constexpr int PTS = fft_points(L);    // spectral points per workgroup
     static constexpr int ITER = PTS / (2 * PW);
     static constexpr int NPASS = (__builtin_ctz(L) + 2) / 3;
+    static constexpr int RG = 256 / PTS;         // row groups of the fused centring
+    static constexpr int MV = (L / 2) / RG;      // centred values per thread
+    static constexpr int ZS = L / 2 + 4;         // float stride of a staged column
     static_assert(ITER >= 1 && PTS % (2 * PW) == 0, "workgroup shape");
+    static_assert(RG * MV == L / 2 && MV % 2 == 0, "centring shape");
 };
+
+// Centring of the workgroup's PTS spectral points, fused ahead of the FFTs
+// (Eqs. (dynspec), (ref); the arithmetic of center_body): thread
+// (c, g) = (tid % PTS, tid / PTS) reads rows g + RG k of column p0 + c,
+// m = L/2 rows in all.  The column mean (or the caller's reference) and,
+// with a result scaling exponent alpha, sigma^-alpha are FP64 sums reduced
+// through LDS; the centred values (FP64, then rounded to float) stay in
+// registers; the column norm gives the per-band scales, which go to s_sc
+// and to the job's scale vectors (the contraction reads them there).
+template <int L>
+__device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, float (&xf)[FftCfg<L>::MV],
+                                  float* s_sc, double* red) {
+    constexpr int PTS = FftCfg<L>::PTS, RG = FftCfg<L>::RG, MV = FftCfg<L>::MV;
+    const int c = tid % PTS, g = tid / PTS;
+    const int64_t col = p0 + c;
+    const bool valid = col < J.n;
+    double v[MV];
+#pragma unroll
+    for (int k = 0; k < MV; ++k) v[k] = valid ? load_in(J, g + (int64_t)RG * k, col) : 0.0;
+    auto colsum = [&](double x) {
+        red[g * PTS + c] = x;
+        __syncthreads();
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < RG; ++q) t += red[q * PTS + c];
+        __syncthreads();
+        return t;
+    };
+    double mean;
+    if (J.ref) {
+        mean = valid ? J.ref[col] : 0.0;
+    } else {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < MV; k += 2) {
+            s0 += v[k];
+            s1 += v[k + 1];
+        }
+        mean = colsum(s0 + s1) / (double)J.m;
+    }
+    double gsc = 1.0;   // sigma^-alpha of this column
+    if (J.alpha != 0.0) {
+        double q0 = 0.0;
+#pragma unroll
+        for (int k = 0; k < MV; ++k) q0 += (v[k] - mean) * (v[k] - mean);
+        const double sd = sqrt(colsum(valid ? q0 : 0.0) / (double)(J.m - 1));
+        if (sd > 0.0) gsc = pow(sd, -J.alpha);
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int k = 0; k < MV; ++k) {
+        const double x = valid ? (v[k] - mean) * gsc : 0.0;
+        nrm += x * x;
+        xf[k] = (float)x;
+    }
+    const double r = sqrt(colsum(nrm));
+    if (g == 0) {
+        float sa = 1.0f, sb = 1.0f;
+        if (J.scale) {
+            sa = pow2_scale(J.qhalf, J.boundA * r);
+            sb = pow2_scale(J.qhalf, J.boundB * r);
+        }
+        s_sc[c] = sa;
+        s_sc[PTS + c] = sb;
+        if (J.sA) J.sA[col] = sa;
+        if (J.sB) J.sB[col] = sb;
+    }
+}
 
 // This thread's twiddles: pass q (stride NS, radix R) multiplies input r of
 // its butterfly b by exp(-2 pi i r k / (NS R)), k = (t + b G) mod NS.
@@ -908,7 +980,8 @@ __device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const flo
 // block, consecutive pairs consecutive points (one contiguous run per
 // block); row layout: consecutive lanes cover consecutive rows of a point.
 // seq (time basis): the rows are the sequence itself -- A the centred
-// spectrum, B the correlation r = conj(U) held in the pair's buffer.
+// spectrum staged in the pair's buffer, B the correlation r = conj(U) held
+// there.
 template <int P, int L>
 __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs, int off, int tid,
                                 bool isB, bool rot, bool zero_nyq, bool seq, const float* s_sc, int pt0) {
@@ -933,7 +1006,7 @@ __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs
             x[e] = (pt & 1) ? -u.y : u.x;
         }
     } else {
-        const float4* src = (const float4*)((const float*)J.yt + (i0 + pt) * J.kt + 8 * hb);
+        const float4* src = (const float4*)((const float*)Z + (pt & 1) * FftCfg<L>::ZS + 8 * hb);
         const float4 a = src[0], b = src[1];
         x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
         x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
@@ -953,6 +1026,7 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
     using C = FftCfg<L>;
     __shared__ float2 s_buf[C::PW * C::PAIR];
     __shared__ float s_sc[2 * C::PTS];
+    __shared__ double s_red[256];
     int lb;
     const PrepJob J = src.get(blockIdx.x, lb);
     const int tid = threadIdx.x, grp = tid / C::G, t = tid % C::G;
@@ -966,24 +1040,33 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
     float gr[8];   // Noda multiplier G(t + r G)
 #pragma unroll
     for (int r = 0; r < 8; ++r) gr[r] = noda ? ((const float*)(tab + L))[t + r * C::G] : 0.0f;
-    if (tid < 2 * C::PTS) {
-        const float* sp = tid < C::PTS ? J.sA : J.sB;
-        s_sc[tid] = sp != nullptr ? sp[p0 + (tid % C::PTS)] : 0.0f;
-    }
-    __syncthreads();
-    const float* Y = (const float*)J.yt;
+    float xf[C::MV];
+    fft_center<L>(J, p0, tid, xf, s_sc, s_red);
     float2* mine = s_buf + grp * C::PAIR;
     int off = 0;   // buffer holding the last FFT output (all pairs alike)
 #pragma unroll 1
     for (int it = 0; it < C::ITER; ++it) {
         const int pt0 = it * 2 * C::PW;
         const int64_t i0 = p0 + pt0;
-        const float* y1 = Y + (i0 + 2 * grp) * J.kt;
+        // stage the pass's 2 PW centred columns in buffer `off`, which the
+        // first FFT pass leaves alone (its second pass overwrites it, after
+        // a barrier that every read of the staged values precedes)
+        __syncthreads();   // the previous pass's readers of buffer `off` are done
+        {
+            const int lc = tid % C::PTS - pt0, g = tid / C::PTS;
+            if (lc >= 0 && lc < 2 * C::PW) {
+                float* zt = (float*)(s_buf + (lc >> 1) * C::PAIR + off) + (lc & 1) * C::ZS;
+#pragma unroll
+                for (int k = 0; k < C::MV; ++k) zt[g + C::RG * k] = xf[k];
+            }
+        }
+        __syncthreads();
+        const float* y1 = (const float*)(mine + off);
         float2 v[8];
         if (tbasis) fft_emit<P, L>(J, i0, s_buf, off, tid, false, false, false, true, s_sc, pt0);
         if (!tbasis || noda) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = make_float2(y1[t + r * C::G], y1[J.kt + t + r * C::G]);
+            for (int r = 0; r < 4; ++r) v[r] = make_float2(y1[t + r * C::G], y1[C::ZS + t + r * C::G]);
 #pragma unroll
             for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
             off = fft_run<L, true>(v, mine, off ^ C::BUF, tw, t);

@@ -520,8 +520,8 @@ def test_fft_transform_time_basis(gpu, prec, m, n):
         check_homo_structure(phi, psi)
         assert rel_fro(phi, phi_o) <= TOL[prec]
         assert rel_fro(psi, psi_o) <= TOL[prec]
-    if prec != "bf16":
-        assert np.array_equal(a[0], b[0])   # A is the centred spectrum on both paths
+    # A is the centred spectrum on both paths (centred by different kernels)
+    assert rel_fro(a[0], b[0]) <= 1e-6 if prec != "bf16" else TOL[prec]
 
 
 def test_fft_transform_hetero_ref_scaled(gpu):
