@@ -15,6 +15,13 @@
 //                     for the reduced formats); the epilogue scales, rounds
 //                     (RNE) and packs the contraction operands, zero padded
 //                     (panel-blocked for the 16-bit formats).
+//   fft_tables_kernel, fft_transform_kernel
+//                     for power-of-two m in [128, 1024] (reduced formats)
+//                     in place of the three kernels above: twiddles and the
+//                     Noda multiplier, then per workgroup the centring (FP64)
+//                     fused with radix FFTs in LDS that produce the same
+//                     packed operands (A from the spectra, Noda's B through
+//                     an FFT correlation).
 //   corr2_kernel, corr_kernel
 //                     MFMA GEMM over output tiles: Phi = c A1^T A2,
 //                     Psi = c A1^T B2 (Eq. (disint2d) evaluated as a real
