@@ -563,6 +563,26 @@ def test_long_perturbation_axis(gpu, prec, m, n):
     assert rel_fro(psi, psi_o) <= TOL[prec]
 
 
+def test_max_n_heterocorrelation(gpu):
+    """n1 at the plan's limit (2^24 spectral points): 64-bit offsets through
+    the workspace, the operand planes and the output; sampled entries,
+    including the last rows, against the oracle."""
+    m, n1, n2 = 3, 1 << 24, 3
+    rng = np.random.default_rng(520)
+    S1 = rng.standard_normal((m, n1)) + 1.0
+    S2 = rng.standard_normal((m, n2)) - 2.0
+    i = np.concatenate([rng.integers(0, n1, 3000), [n1 - 1, n1 - 2, 0, (1 << 23) + 5]])
+    j = np.concatenate([rng.integers(0, n2, 3000), [n2 - 1, 0, 1, 2]])
+    po, qo = oracle.corr2d_entries(S1, i, j, S2=S2)
+    phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), prec="f32")
+    import torch
+    idx = torch.as_tensor(i * n2 + j, device=gpu)
+    gp = phi.reshape(-1)[idx].double().cpu().numpy()
+    gq = psi.reshape(-1)[idx].double().cpu().numpy()
+    assert rel_fro(gp, po) <= TOL["f32"]
+    assert rel_fro(gq, qo) <= TOL["f32"]
+
+
 def test_wide_heterocorrelation(gpu):
     m, n1, n2 = 6, 120000, 37
     S1, S2 = _rand(m, n1, 510), _rand(m, n2, 511)

@@ -40,24 +40,28 @@ def large():
     return S, i, j, phi_o, psi_o
 
 
-@pytest.mark.parametrize("prec,basis,tol", [
-    ("split_bf16", "fourier", TOL["split_bf16"]),
-    ("f32", "fourier", TOL["f32"]),
-    ("bf16", "time", BF16_BAND_TOL),
-    ("bf16", "fourier", TOL["bf16"]),
+@pytest.mark.parametrize("prec,basis,tol,flags", [
+    ("split_bf16", "fourier", TOL["split_bf16"], 0),
+    ("split_bf16", "fourier", TOL["split_bf16"], B.FLAG_TRANSFORM_MATMUL),
+    ("f32", "fourier", TOL["f32"], 0),
+    ("bf16", "time", BF16_BAND_TOL, 0),
+    ("bf16", "fourier", TOL["bf16"], 0),
 ])
-def test_large_homo_sampled(gpu, large, prec, basis, tol):
-    """m=256, n=16384 band workload, upper triangle stored (the bench's launch)."""
+def test_large_homo_sampled(gpu, large, prec, basis, tol, flags):
+    """m=256, n=16384 band workload, upper triangle stored (the bench's launch),
+    through the radix FFT transform (the default at this m) and, forced by the
+    flag, the table product."""
     import torch
     S, i, j, phi_o, psi_o = large
     n = S.shape[1]
     phi, psi, plan, ws = B.homo(torch.as_tensor(S, device=gpu), prec=prec, basis=basis,
-                                layout="upper_packed")
+                                layout="upper_packed", flags=flags)
+    assert B.corr2d_plan_get_info(plan.handle).transform == (0 if flags else 1)
     idx = torch.as_tensor(packed_index(i, j, n), device=gpu)
     g_phi = phi[idx].double().cpu().numpy()
     g_psi = psi[idx].double().cpu().numpy()
     e_phi, e_psi = rel_fro(g_phi, phi_o), rel_fro(g_psi, psi_o)
-    print(f"large {prec}/{basis}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
+    print(f"large {prec}/{basis}/flags={flags}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
     assert e_phi <= tol and e_psi <= tol
     d = torch.as_tensor(packed_index(np.arange(n), np.arange(n), n), device=gpu)
     assert torch.all(psi[d] == 0)
