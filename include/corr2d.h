@@ -130,8 +130,8 @@ typedef enum corr2d_dtype { CORR2D_DTYPE_F64 = 0, CORR2D_DTYPE_F32 = 1 } corr2d_
 #define CORR2D_FLAG_TRANSFORM_MATMUL 0x10u /* perturbation-axis transform as the MFMA
                                            product with the table also where the
                                            radix FFT applies (power-of-two
-                                           128 <= m <= 1024, not FP64; Fourier
-                                           basis, or time basis with Noda's kernel) */
+                                           128 <= m <= 1024; Fourier basis, or
+                                           time basis with Noda's kernel)      */
 
 typedef struct corr2d_desc {
     int64_t m;          /* perturbation steps, >= 2 (Eq. (disFT): equidistant)   */

@@ -339,12 +339,12 @@ int transform_blocks(const Geo& g, int prec) {
     return (int)((g.n_pad / 64) * ((g.rows_pad + 255) / 256));
 }
 
-// The radix FFT transform serves power-of-two m in [128, 1024] in the
-// reduced precisions: the Fourier basis, and the time basis with Noda's
-// kernel (B = N Yc as an FFT correlation).  FP64 keeps the FP64 MFMA
-// product, and a flag asks for the product everywhere.
+// The radix FFT transform (FP64 for the FP64 path, else FP32) serves
+// power-of-two m in [128, 1024]: the Fourier basis, and the time basis with
+// Noda's kernel (B = N Yc as an FFT correlation).  A flag asks for the
+// table product everywhere.
 bool use_fft(const corr2d_desc* d, int64_t m) {
-    if (d->flags & CORR2D_FLAG_TRANSFORM_MATMUL || d->prec == CORR2D_PREC_F64) return false;
+    if (d->flags & CORR2D_FLAG_TRANSFORM_MATMUL) return false;
     if (d->basis == CORR2D_BASIS_TIME && d->hilbert != CORR2D_HILBERT_NODA) return false;
     return m >= 128 && m <= 1024 && (m & (m - 1)) == 0;
 }

@@ -16,8 +16,8 @@
 //                     (RNE) and packs the contraction operands, zero padded
 //                     (panel-blocked for the 16-bit formats).
 //   fft_tables_kernel, fft_transform_kernel
-//                     for power-of-two m in [128, 1024] (reduced formats)
-//                     in place of the three kernels above: twiddles and the
+//                     for power-of-two m in [128, 1024] (FP64 for the FP64
+//                     path, else FP32) in place of the three kernels above: twiddles and the
 //                     Noda multiplier, then per workgroup the centring (FP64)
 //                     fused with radix FFTs in LDS that produce the same
 //                     packed operands (A from the spectra, Noda's B through
@@ -667,11 +667,12 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
 }
 
 // =========================================================================
-// Radix FFT transform (power-of-two m, Fourier basis, FP32)
+// Radix FFT transform (power-of-two m)
 // =========================================================================
 // For m = 2^s, 128 <= m <= 1024, the perturbation-axis transform runs as
 // FFTs of length L = 2m in LDS instead of the product with the table (m^2
-// work per spectral point becomes m log m).  Two spectral points y1, y2
+// work per spectral point becomes m log m), in FP64 for the FP64 path and
+// FP32 otherwise.  Two spectral points y1, y2
 // travel as one complex sequence z = y1 + i y2, zero padded to L:
 //   Z = FFT_L(z).  Its even bins are the m-point spectra of the pair,
 //       Y1(p) = (Z(2p) + conj Z(L-2p)) / 2 and Y2(p) = (Z(2p) - conj Z(L-2p)) / 2i
@@ -694,42 +695,50 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
 // LDS indices are padded by one entry in 16 against bank conflicts.  The
 // twiddles of each pass and the Noda multiplier depend only on the thread's
 // index within its pair, so each thread keeps its own in registers.
-__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ inline float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Complex values are float2 (reduced formats) or double2 (FP64 path).
+template <class V> struct Scal;
+template <> struct Scal<float2> { using T = float; };
+template <> struct Scal<double2> { using T = double; };
+__device__ inline float2 cx(float a, float b) { return make_float2(a, b); }
+__device__ inline double2 cx(double a, double b) { return make_double2(a, b); }
+template <class V> __device__ inline V cadd(V a, V b) { return cx(a.x + b.x, a.y + b.y); }
+template <class V> __device__ inline V csub(V a, V b) { return cx(a.x - b.x, a.y - b.y); }
+template <class V> __device__ inline V cmul(V a, V b) {
+    return cx(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ inline float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
+template <class V> __device__ inline V mul_mi(V a) { return cx(a.y, -a.x); }   // a * (-i)
 __device__ inline int fpad(int i) { return i + (i >> 4); }
 
 // In-register forward DFTs (exp(-2 pi i j k / R)) of v[O .. O+R-1], outputs
 // in natural order.
-template <int O>
-__device__ inline void dft2(float2 (&v)[8]) {
-    const float2 a = v[O];
+template <int O, class V>
+__device__ inline void dft2(V (&v)[8]) {
+    const V a = v[O];
     v[O] = cadd(a, v[O + 1]);
     v[O + 1] = csub(a, v[O + 1]);
 }
-template <int O, int S = 1>
-__device__ inline void dft4(float2 (&v)[8]) {
-    const float2 a0 = cadd(v[O], v[O + 2 * S]), a1 = csub(v[O], v[O + 2 * S]);
-    const float2 a2 = cadd(v[O + S], v[O + 3 * S]), a3 = mul_mi(csub(v[O + S], v[O + 3 * S]));
+template <int O, int S = 1, class V>
+__device__ inline void dft4(V (&v)[8]) {
+    const V a0 = cadd(v[O], v[O + 2 * S]), a1 = csub(v[O], v[O + 2 * S]);
+    const V a2 = cadd(v[O + S], v[O + 3 * S]), a3 = mul_mi(csub(v[O + S], v[O + 3 * S]));
     v[O] = cadd(a0, a2);
     v[O + 2 * S] = csub(a0, a2);
     v[O + S] = cadd(a1, a3);
     v[O + 3 * S] = csub(a1, a3);
 }
-__device__ inline void dft8(float2 (&v)[8]) {
-    constexpr float r = 0.70710678118654752f;
+template <class V>
+__device__ inline void dft8(V (&v)[8]) {
+    using S = typename Scal<V>::T;
+    constexpr S r = S(0.70710678118654752440);
     // E = DFT4 of the even inputs, O = DFT4 of the odd ones (in place, stride 2)
     dft4<0, 2>(v);
     dft4<1, 2>(v);
     // X_k = E_k + W^k O_k, X_(k+4) = E_k - W^k O_k, W = exp(-i pi / 4)
-    const float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    const float2 o0 = v[1];
-    const float2 o1 = make_float2(r * (v[3].x + v[3].y), r * (v[3].y - v[3].x));
-    const float2 o2 = mul_mi(v[5]);
-    const float2 o3 = make_float2(r * (v[7].y - v[7].x), -r * (v[7].x + v[7].y));
+    const V e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    const V o0 = v[1];
+    const V o1 = cx(r * (v[3].x + v[3].y), r * (v[3].y - v[3].x));
+    const V o2 = mul_mi(v[5]);
+    const V o3 = cx(r * (v[7].y - v[7].x), -r * (v[7].x + v[7].y));
     v[0] = cadd(e0, o0);
     v[4] = csub(e0, o0);
     v[1] = cadd(e1, o1);
@@ -742,15 +751,17 @@ __device__ inline void dft8(float2 (&v)[8]) {
 
 // dft8 of inputs whose last four are zero (the zero-padded half of a
 // first pass).
-__device__ inline void dft8_half(float2 (&v)[8]) {
-    constexpr float r = 0.70710678118654752f;
-    const float2 e0 = cadd(v[0], v[2]), e2 = csub(v[0], v[2]);
-    const float2 e1 = cadd(v[0], mul_mi(v[2])), e3 = csub(v[0], mul_mi(v[2]));
-    const float2 q0 = cadd(v[1], v[3]), q2 = csub(v[1], v[3]);
-    const float2 q1 = cadd(v[1], mul_mi(v[3])), q3 = csub(v[1], mul_mi(v[3]));
-    const float2 o1 = make_float2(r * (q1.x + q1.y), r * (q1.y - q1.x));
-    const float2 o2 = mul_mi(q2);
-    const float2 o3 = make_float2(r * (q3.y - q3.x), -r * (q3.x + q3.y));
+template <class V>
+__device__ inline void dft8_half(V (&v)[8]) {
+    using S = typename Scal<V>::T;
+    constexpr S r = S(0.70710678118654752440);
+    const V e0 = cadd(v[0], v[2]), e2 = csub(v[0], v[2]);
+    const V e1 = cadd(v[0], mul_mi(v[2])), e3 = csub(v[0], mul_mi(v[2]));
+    const V q0 = cadd(v[1], v[3]), q2 = csub(v[1], v[3]);
+    const V q1 = cadd(v[1], mul_mi(v[3])), q3 = csub(v[1], mul_mi(v[3]));
+    const V o1 = cx(r * (q1.x + q1.y), r * (q1.y - q1.x));
+    const V o2 = mul_mi(q2);
+    const V o3 = cx(r * (q3.y - q3.x), -r * (q3.x + q3.y));
     v[0] = cadd(e0, q0);
     v[4] = csub(e0, q0);
     v[1] = cadd(e1, o1);
@@ -771,7 +782,7 @@ template <int L> struct FftCfg {
     static constexpr int NPASS = (__builtin_ctz(L) + 2) / 3;
     static constexpr int RG = 256 / PTS;         // row groups of the fused centring
     static constexpr int MV = (L / 2) / RG;      // centred values per thread
-    static constexpr int ZS = L / 2 + 4;         // float stride of a staged column
+    static constexpr int ZS = L / 2 + 4;         // scalar stride of a staged column
     static_assert(ITER >= 1 && PTS % (2 * PW) == 0, "workgroup shape");
     static_assert(RG * MV == L / 2 && MV % 2 == 0, "centring shape");
 };
@@ -782,10 +793,11 @@ template <int L> struct FftCfg {
 // m = L/2 rows in all.  The column mean (or the caller's reference) and,
 // with a result scaling exponent alpha, sigma^-alpha are FP64 sums reduced
 // through LDS; the centred values (FP64, then rounded to float) stay in
-// registers; the column norm gives the per-band scales, which go to s_sc
-// and to the job's scale vectors (the contraction reads them there).
-template <int L>
-__device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, float (&xf)[FftCfg<L>::MV],
+// registers (as float for the reduced formats); the column norm gives the
+// per-band scales, which go to s_sc and to the job's scale vectors (the
+// contraction reads them there).
+template <int L, class S>
+__device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, S (&xf)[FftCfg<L>::MV],
                                   float* s_sc, double* red) {
     constexpr int PTS = FftCfg<L>::PTS, RG = FftCfg<L>::RG, MV = FftCfg<L>::MV;
     const int c = tid % PTS, g = tid / PTS;
@@ -828,7 +840,7 @@ __device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, float (
     for (int k = 0; k < MV; ++k) {
         const double x = valid ? (v[k] - mean) * gsc : 0.0;
         nrm += x * x;
-        xf[k] = (float)x;
+        xf[k] = (S)x;
     }
     const double r = sqrt(colsum(nrm));
     if (g == 0) {
@@ -846,10 +858,10 @@ __device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, float (
 
 // This thread's twiddles: pass q (stride NS, radix R) multiplies input r of
 // its butterfly b by exp(-2 pi i r k / (NS R)), k = (t + b G) mod NS.
-template <int L> struct FftTw { float2 w[FftCfg<L>::NPASS][8]; };
+template <int L, class V> struct FftTw { V w[FftCfg<L>::NPASS][8]; };
 
-template <int L, int NS = 1, int PASS = 0>
-__device__ inline void fft_twiddles(FftTw<L>& tw, const float2* tab, int t) {
+template <int L, class V, int NS = 1, int PASS = 0>
+__device__ inline void fft_twiddles(FftTw<L, V>& tw, const V* tab, int t) {
     constexpr int R = (L / NS) >= 8 ? 8 : L / NS, NB = 8 / R, STEP = L / (NS * R);
     if constexpr (NS > 1) {
 #pragma unroll
@@ -857,15 +869,15 @@ __device__ inline void fft_twiddles(FftTw<L>& tw, const float2* tab, int t) {
 #pragma unroll
             for (int r = 1; r < R; ++r) tw.w[PASS][b * R + r] = tab[r * ((t + b * FftCfg<L>::G) & (NS - 1)) * STEP];
     }
-    if constexpr (NS * R < L) fft_twiddles<L, NS * R, PASS + 1>(tw, tab, t);
+    if constexpr (NS * R < L) fft_twiddles<L, V, NS * R, PASS + 1>(tw, tab, t);
 }
 
 // One Stockham pass of radix R at stride NS: butterfly j (this thread's
 // j = t + b G, b < 8/R) takes inputs j + r L/R (held in v), applies the
 // twiddles exp(-2 pi i r (j mod NS) / (NS R)), transforms, and writes output
 // r to (j div NS) NS R + (j mod NS) + r NS.
-template <int L, int R, int NS, bool HALF>
-__device__ inline void fft_pass(float2 (&v)[8], float2* dst, const float2 (&tw)[8], int t) {
+template <int L, int R, int NS, bool HALF, class V>
+__device__ inline void fft_pass(V (&v)[8], V* dst, const V (&tw)[8], int t) {
     constexpr int G = L / 8, NB = 8 / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -889,8 +901,8 @@ __device__ inline void fft_pass(float2 (&v)[8], float2* dst, const float2 (&tw)[
     }
 }
 
-template <int L, int R>
-__device__ inline void fft_load(float2 (&v)[8], const float2* src, int t) {
+template <int L, int R, class V>
+__device__ inline void fft_load(V (&v)[8], const V* src, int t) {
     constexpr int G = L / 8, NB = 8 / R;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -902,15 +914,15 @@ __device__ inline void fft_load(float2 (&v)[8], const float2* src, int t) {
 // thread holds (HALF: v[4..7] are zero).  Passes write base + off and
 // base + (off ^ BUF) in turn; returns the offset of the buffer holding the
 // natural-order output (after a workgroup barrier).
-template <int L, bool HALF, int NS = 1, int PASS = 0>
-__device__ inline int fft_run(float2 (&v)[8], float2* base, int off, const FftTw<L>& tw, int t) {
+template <int L, bool HALF, class V, int NS = 1, int PASS = 0>
+__device__ inline int fft_run(V (&v)[8], V* base, int off, const FftTw<L, V>& tw, int t) {
     constexpr int R = (L / NS) >= 8 ? 8 : L / NS;
     fft_pass<L, R, NS, HALF && NS == 1>(v, base + off, tw.w[PASS], t);
     __syncthreads();
     if constexpr (NS * R < L) {
         constexpr int R2 = (L / (NS * R)) >= 8 ? 8 : L / (NS * R);
         fft_load<L, R2>(v, base + off, t);
-        return fft_run<L, HALF, NS * R, PASS + 1>(v, base, off ^ FftCfg<L>::BUF, tw, t);
+        return fft_run<L, HALF, V, NS * R, PASS + 1>(v, base, off ^ FftCfg<L>::BUF, tw, t);
     } else {
         return off;
     }
@@ -921,16 +933,15 @@ __device__ inline int fft_run(float2 (&v)[8], float2* base, int off, const FftTw
 // is Re Y(0), rows 2p-1, 2p are sqrt2 Re Y(p), sqrt2 Im Y(p), row m-1 is
 // Re Y(m/2).  rot: rows of i Y with DC and Nyquist zero; zero_nyq: the
 // Nyquist row is zero.
-template <int L>
-__device__ inline void packed_rows8(const float2* Z, bool second, int k0, bool rot, bool zero_nyq,
-                                    float (&x)[8]) {
+template <int L, class V, class S>
+__device__ inline void packed_rows8(const V* Z, bool second, int k0, bool rot, bool zero_nyq, S (&x)[8]) {
     constexpr int M = L / 2;
-    constexpr float hf = 0.5f, s2 = 0.70710678118654752f;
-    float yr[5], yi[5];   // 2 Re Y(p), 2 Im Y(p) for p = k0/2 .. k0/2 + 4
+    constexpr S hf = S(0.5), s2 = S(0.70710678118654752440);
+    S yr[5], yi[5];   // 2 Re Y(p), 2 Im Y(p) for p = k0/2 .. k0/2 + 4
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const int p = (k0 >> 1) + q;
-        const float2 a = Z[fpad(2 * p)], b = Z[fpad((L - 2 * p) & (L - 1))];
+        const V a = Z[fpad(2 * p)], b = Z[fpad((L - 2 * p) & (L - 1))];
         yr[q] = second ? a.y + b.y : a.x + b.x;
         yi[q] = second ? b.x - a.x : a.y - b.y;
     }
@@ -942,24 +953,29 @@ __device__ inline void packed_rows8(const float2* Z, bool second, int k0, bool r
         x[4] = s2 * yi[2];
         x[5] = s2 * yr[3];
         x[6] = s2 * yi[3];
-        x[7] = k0 + 7 == M - 1 ? (zero_nyq ? 0.0f : hf * yr[4]) : s2 * yr[4];
+        x[7] = k0 + 7 == M - 1 ? (zero_nyq ? S(0) : hf * yr[4]) : s2 * yr[4];
     } else {
-        x[0] = k0 == 0 ? 0.0f : s2 * yr[0];
+        x[0] = k0 == 0 ? S(0) : s2 * yr[0];
         x[1] = -s2 * yi[1];
         x[2] = s2 * yr[1];
         x[3] = -s2 * yi[2];
         x[4] = s2 * yr[2];
         x[5] = -s2 * yi[3];
         x[6] = s2 * yr[3];
-        x[7] = k0 + 7 == M - 1 ? 0.0f : -s2 * yi[4];
+        x[7] = k0 + 7 == M - 1 ? S(0) : -s2 * yi[4];
     }
 }
 
 // Eight consecutive contraction elements of one operand row (idx a multiple
-// of 8) rounded to the operand format, one vector store per plane.
-template <int P>
-__device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const float (&x)[8]) {
-    if constexpr (P == P_F32) {
+// of 8) rounded to the operand format, one vector store per plane (FP64:
+// stored as they are).
+template <int P, class S>
+__device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const S (&x)[8]) {
+    if constexpr (P == P_F64) {
+        double2* d = (double2*)((double*)p0 + idx);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = make_double2(x[2 * q], x[2 * q + 1]);
+    } else if constexpr (P == P_F32) {
         float4* d = (float4*)((float*)p0 + idx);
         d[0] = make_float4(x[0], x[1], x[2], x[3]);
         d[1] = make_float4(x[4], x[5], x[6], x[7]);
@@ -989,9 +1005,14 @@ __device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const flo
 // seq (time basis): the rows are the sequence itself -- A the centred
 // spectrum staged in the pair's buffer, B the correlation r = conj(U) held
 // there.
+template <int P> using FftV = typename std::conditional<P == P_F64, double2, float2>::type;
+template <int P> using FftS = typename std::conditional<P == P_F64, double, float>::type;
+
 template <int P, int L>
-__device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs, int off, int tid,
+__device__ inline void fft_emit(const PrepJob& J, int64_t i0, const FftV<P>* bufs, int off, int tid,
                                 bool isB, bool rot, bool zero_nyq, bool seq, const float* s_sc, int pt0) {
+    using V = FftV<P>;
+    using S = FftS<P>;
     constexpr int M = L / 2, NP = 2 * FftCfg<L>::PW;
     int pt, hb;
     if constexpr (blocked_layout(P)) {
@@ -1002,21 +1023,20 @@ __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs
         pt = tid / (M / 8);
         hb = tid % (M / 8);
     }
-    const float2* Z = bufs + (pt >> 1) * FftCfg<L>::PAIR + off;
-    float x[8];
+    const V* Z = bufs + (pt >> 1) * FftCfg<L>::PAIR + off;
+    S x[8];
     if (!seq) {
         packed_rows8<L>(Z, pt & 1, 8 * hb, rot, zero_nyq, x);
     } else if (isB) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const float2 u = Z[fpad(8 * hb + e)];
+            const V u = Z[fpad(8 * hb + e)];
             x[e] = (pt & 1) ? -u.y : u.x;
         }
     } else {
-        const float4* src = (const float4*)((const float*)Z + (pt & 1) * FftCfg<L>::ZS + 8 * hb);
-        const float4 a = src[0], b = src[1];
-        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+        const S* src = (const S*)Z + (pt & 1) * FftCfg<L>::ZS + 8 * hb;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = src[e];
     }
     const float sc = s_sc[(isB ? FftCfg<L>::PTS : 0) + pt0 + pt];
 #pragma unroll
@@ -1028,10 +1048,11 @@ __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const float2* bufs
 
 template <int P, int LOG2L, class Src>
 __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
-    static_assert(P != P_F64, "the FP64 path keeps the transform GEMM");
     constexpr int L = 1 << LOG2L;
     using C = FftCfg<L>;
-    __shared__ float2 s_buf[C::PW * C::PAIR];
+    using V = FftV<P>;
+    using S = FftS<P>;
+    __shared__ V s_buf[C::PW * C::PAIR];
     __shared__ float s_sc[2 * C::PTS];
     __shared__ double s_red[256];
     int lb;
@@ -1041,15 +1062,15 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
     const bool rcompat = J.hilbert == H_R_COMPAT;
     const bool tbasis = J.basis == B_TIME;   // (Noda's kernel only)
     const int64_t p0 = (int64_t)lb * C::PTS;   // first spectral point of the workgroup
-    const float2* tab = (const float2*)J.table;
-    FftTw<L> tw;
+    const V* tab = (const V*)J.table;
+    FftTw<L, V> tw;
     fft_twiddles<L>(tw, tab, t);
-    float gr[8];   // Noda multiplier G(t + r G)
+    S gr[8];   // Noda multiplier G(t + r G)
 #pragma unroll
-    for (int r = 0; r < 8; ++r) gr[r] = noda ? ((const float*)(tab + L))[t + r * C::G] : 0.0f;
-    float xf[C::MV];
+    for (int r = 0; r < 8; ++r) gr[r] = noda ? ((const S*)(tab + L))[t + r * C::G] : S(0);
+    S xf[C::MV];
     fft_center<L>(J, p0, tid, xf, s_sc, s_red);
-    float2* mine = s_buf + grp * C::PAIR;
+    V* mine = s_buf + grp * C::PAIR;
     int off = 0;   // buffer holding the last FFT output (all pairs alike)
 #pragma unroll 1
     for (int it = 0; it < C::ITER; ++it) {
@@ -1062,20 +1083,20 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
         {
             const int lc = tid % C::PTS - pt0, g = tid / C::PTS;
             if (lc >= 0 && lc < 2 * C::PW) {
-                float* zt = (float*)(s_buf + (lc >> 1) * C::PAIR + off) + (lc & 1) * C::ZS;
+                S* zt = (S*)(s_buf + (lc >> 1) * C::PAIR + off) + (lc & 1) * C::ZS;
 #pragma unroll
                 for (int k = 0; k < C::MV; ++k) zt[g + C::RG * k] = xf[k];
             }
         }
         __syncthreads();
-        const float* y1 = (const float*)(mine + off);
-        float2 v[8];
+        const S* y1 = (const S*)(mine + off);
+        V v[8];
         if (tbasis) fft_emit<P, L>(J, i0, s_buf, off, tid, false, false, false, true, s_sc, pt0);
         if (!tbasis || noda) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = make_float2(y1[t + r * C::G], y1[C::ZS + t + r * C::G]);
+            for (int r = 0; r < 4; ++r) v[r] = cx(y1[t + r * C::G], y1[C::ZS + t + r * C::G]);
 #pragma unroll
-            for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
+            for (int r = 4; r < 8; ++r) v[r] = cx(S(0), S(0));
             off = fft_run<L, true>(v, mine, off ^ C::BUF, tw, t);
         }
         if (!tbasis) fft_emit<P, L>(J, i0, s_buf, off, tid, false, false, rcompat, false, s_sc, pt0);
@@ -1084,8 +1105,8 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
             // conj(i G Z): the inverse transform as a forward one
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                const float2 z = mine[off + fpad(t + r * C::G)];
-                v[r] = make_float2(-gr[r] * z.y, -gr[r] * z.x);
+                const V z = mine[off + fpad(t + r * C::G)];
+                v[r] = cx(-gr[r] * z.y, -gr[r] * z.x);
             }
             off = fft_run<L, false>(v, mine, off ^ C::BUF, tw, t);
             if (tbasis) {
@@ -1094,11 +1115,11 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
                 // r = conj of that, entries from m on dropped
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float2 u = mine[off + fpad(t + r * C::G)];
-                    v[r] = make_float2(u.x, -u.y);
+                    const V u = mine[off + fpad(t + r * C::G)];
+                    v[r] = cx(u.x, -u.y);
                 }
 #pragma unroll
-                for (int r = 4; r < 8; ++r) v[r] = make_float2(0.0f, 0.0f);
+                for (int r = 4; r < 8; ++r) v[r] = cx(S(0), S(0));
                 off = fft_run<L, true>(v, mine, off ^ C::BUF, tw, t);
                 fft_emit<P, L>(J, i0, s_buf, off, tid, true, false, false, false, s_sc, pt0);
             }
@@ -1108,8 +1129,8 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
 
 // Tables of the radix FFT transform, L = 2m: tw[w] = exp(-2 pi i w / L) and,
 // for Noda's kernel, g[w] = (2/L) sum_{d=1}^{m-1} sin(2 pi w d / L) / (pi d)
-// (FP64 sums, stored as float; g follows the L twiddles).  One workgroup
-// per w.
+// (FP64 sums, stored as double for the FP64 path, else as float; g follows
+// the L twiddles).  One workgroup per w.
 template <class Src>
 __global__ __launch_bounds__(256) void fft_tables_kernel(Src src) {
     __shared__ double part[256];
@@ -1134,9 +1155,15 @@ __global__ __launch_bounds__(256) void fft_tables_kernel(Src src) {
     if (tid == 0) {
         double sv, cv;
         sincospi(2.0 * (double)w / (double)L, &sv, &cv);
-        float2* tw = (float2*)T.table;
-        tw[w] = make_float2((float)cv, (float)-sv);
-        ((float*)(tw + L))[w] = (float)(2.0 * part[0] / (double)L);
+        if (T.f64) {
+            double2* tw = (double2*)T.table;
+            tw[w] = make_double2(cv, -sv);
+            ((double*)(tw + L))[w] = 2.0 * part[0] / (double)L;
+        } else {
+            float2* tw = (float2*)T.table;
+            tw[w] = make_float2((float)cv, (float)-sv);
+            ((float*)(tw + L))[w] = (float)(2.0 * part[0] / (double)L);
+        }
     }
 }
 
@@ -2021,6 +2048,7 @@ static hipError_t launch_fft_p(int log2l, const PrepSrcInline& src, int blocks, 
 
 hipError_t launch_fft_transform(int prec, int log2l, const PrepSrcInline& src, int blocks, hipStream_t s) {
     switch (prec) {
+    case P_F64: return launch_fft_p<P_F64>(log2l, src, blocks, s);
     case P_F32: return launch_fft_p<P_F32>(log2l, src, blocks, s);
     case P_SPLIT: return launch_fft_p<P_SPLIT>(log2l, src, blocks, s);
     case P_BF16: return launch_fft_p<P_BF16>(log2l, src, blocks, s);

@@ -197,16 +197,16 @@ def test_plan_info():
 @pytest.mark.parametrize("kw,fft", [
     (dict(m=256), 1), (dict(m=128), 1), (dict(m=512), 1), (dict(m=1024), 1),
     (dict(m=64), 0), (dict(m=127), 0), (dict(m=384), 0), (dict(m=2048), 0),
-    (dict(m=256, prec="f64"), 0), (dict(m=256, basis="time"), 1),
+    (dict(m=256, prec="f64"), 1), (dict(m=100, prec="f64"), 0), (dict(m=256, basis="time"), 1),
     (dict(m=256, basis="time", hilbert="circular"), 0),
     (dict(m=256, flags=B.FLAG_TRANSFORM_MATMUL), 0),
     (dict(m=256, hilbert="circular"), 1), (dict(m=256, hilbert="r_compat"), 1),
     (dict(m=128, n2=40), 1), (dict(m=256, prec="fp8_e4m3"), 1),
 ])
 def test_transform_selection(kw, fft):
-    """The radix FFT transform serves power-of-two 128 <= m <= 1024 outside
-    FP64 (Fourier basis; time basis with Noda's kernel), unless the flag asks
-    for the product."""
+    """The radix FFT transform serves power-of-two 128 <= m <= 1024 (Fourier
+    basis; time basis with Noda's kernel), unless the flag asks for the
+    product."""
     base = dict(n1=300)
     base.update(kw)
     _, h = B.corr2d_plan(B.corr2d_desc_init(**base))

@@ -468,7 +468,7 @@ def test_interpolation_hetero_f32_input_scaled(gpu):
 # --------------------------------------------------------------------------
 # Radix FFT transform (power-of-two 128 <= m <= 1024, Fourier basis)
 # --------------------------------------------------------------------------
-FFT_PRECS = ["f32", "split_bf16", "bf16", "f16", "fp8_e4m3"]
+FFT_PRECS = ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"]
 
 
 def _transform(plan):
@@ -489,7 +489,7 @@ def test_fft_transform_parity(gpu, prec, m, n):
     assert rel_fro(psi, psi_o) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16"])
 @pytest.mark.parametrize("hilbert,norm", [("noda", "noda"), ("circular", "noda"), ("r_compat", "paper")])
 def test_fft_transform_modes_and_matmul_flag(gpu, prec, hilbert, norm):
     """Each asynchronous kernel through the FFT transform against the oracle;
@@ -507,7 +507,7 @@ def test_fft_transform_modes_and_matmul_flag(gpu, prec, hilbert, norm):
     assert rel_fro(a[0], b[0]) <= TOL[prec] and rel_fro(a[1], b[1]) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f32", "split_bf16", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "bf16"])
 @pytest.mark.parametrize("m,n", [(128, 150), (512, 70)])
 def test_fft_transform_time_basis(gpu, prec, m, n):
     """Time basis with Noda's kernel: B = N Yc as an FFT correlation."""
