@@ -361,6 +361,11 @@ bool needs_qn(const corr2d_plan_s* p) {
     return p->d.basis == CORR2D_BASIS_FOURIER && p->d.hilbert == CORR2D_HILBERT_NODA;
 }
 
+// Table-product plans with m <= kPrepMergeMaxM build the table and centre
+// the spectra in one launch (after the optional resampling); the others
+// launch their tables first (FFT plans centre inside the transform).
+bool merged_prep(const corr2d_plan_s* p) { return !p->fft && p->g1.m <= kPrepMergeMaxM; }
+
 // Tables of a single or heterocorrelation plan: the DFT table (and its Q N
 // rows), or the twiddles and Noda multiplier of the radix FFT transform.
 hipError_t launch_prep_tables(const corr2d_plan_s* p, const TableSrcInline& ts, hipStream_t s) {
@@ -738,7 +743,7 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
-    hipError_t e = launch_prep_tables(p, ts, s);
+    hipError_t e = merged_prep(p) ? hipSuccess : launch_prep_tables(p, ts, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     const void* yc = y;
@@ -756,7 +761,10 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     ps.count = 1;
     ps.blocks0 = center_blocks(p->g1);
     // the FFT transform centres the spectra itself
-    if (!p->fft) e = launch_center(ps, ps.blocks0, s);
+    if (merged_prep(p))
+        e = launch_prep(ts, ts.blocks0, needs_qn(p) ? qn_blocks(p->g1.m) : 0, p->g1.m, ps, ps.blocks0, s);
+    else if (!p->fft)
+        e = launch_center(ps, ps.blocks0, s);
     if (e != hipSuccess) return device_fail(e, "center launch");
     if (p->fft) {
         ps.blocks0 = fft_blocks(p->g1);
@@ -795,7 +803,7 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     ts.j[0] = make_table_job(p, p->g1, ws, p->table_off);
     ts.count = 1;
     ts.blocks0 = table_blocks(p->g1);
-    hipError_t e = launch_prep_tables(p, ts, s);
+    hipError_t e = merged_prep(p) ? hipSuccess : launch_prep_tables(p, ts, s);
     if (e != hipSuccess) return device_fail(e, "tables launch");
 
     const void *yc1 = y1, *yc2 = y2;
@@ -816,7 +824,11 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     if (p->interp) ps.j[0].in_f64 = ps.j[1].in_f64 = 1;
     ps.count = 2;
     ps.blocks0 = center_blocks(p->g1);
-    if (!p->fft) e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
+    if (merged_prep(p))
+        e = launch_prep(ts, ts.blocks0, needs_qn(p) ? qn_blocks(p->g1.m) : 0, p->g1.m, ps,
+                        ps.blocks0 + center_blocks(p->g2), s);
+    else if (!p->fft)
+        e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
     if (e != hipSuccess) return device_fail(e, "center launch");
     if (p->fft) {
         ps.blocks0 = fft_blocks(p->g1);

@@ -210,14 +210,13 @@ constexpr int kMaxTwiddle = 4096;
 // Dynamic LDS: cos and sin of 2 pi i / m (m entries each), then
 // hh[d + m] = 1/(pi d) for -m < d < m (2m entries); 32 m bytes in all.
 template <class Src>
-__global__ __launch_bounds__(256) void tables_kernel(Src src) {
-    extern __shared__ double tw_lds[];
+__device__ inline void tables_body(const Src& src, int blk, double* tw_lds) {
     int lb;
-    const TableJob T = src.get(blockIdx.x, lb);
+    const TableJob T = src.get(blk, lb);
     double* tc = tw_lds;
     double* ts = tw_lds + T.m;
     double* hh = tw_lds + 2 * T.m;
-    if (blockIdx.x == 0 && src.counter && (int)threadIdx.x < src.ncounters) src.counter[threadIdx.x] = 0;
+    if (blk == 0 && src.counter && (int)threadIdx.x < src.ncounters) src.counter[threadIdx.x] = 0;
     for (int64_t i = threadIdx.x; i < T.m; i += blockDim.x) {
         double sv, cv;
         sincospi(2.0 * (double)i / (double)T.m, &sv, &cv);
@@ -239,6 +238,12 @@ __global__ __launch_bounds__(256) void tables_kernel(Src src) {
     else ((float*)T.table)[e] = (float)v;
 }
 
+template <class Src>
+__global__ __launch_bounds__(256) void tables_kernel(Src src) {
+    extern __shared__ double tw_lds[];
+    tables_body(src, blockIdx.x, tw_lds);
+}
+
 // Rows of Q N (Fourier basis, Noda's kernel) in O(m) per frequency.  With
 // theta = 2 pi p / m and d = j - l, a cosine row of Q gives
 //   sum_{l != j} cos(theta l) / (pi (j - l))
@@ -250,11 +255,10 @@ __global__ __launch_bounds__(256) void tables_kernel(Src src) {
 // rows 2p-1, 2p, or the Nyquist row of an even m (p = m/2); the prefix sums
 // (FP64) are scanned in LDS, 16 m bytes.
 template <class Src>
-__global__ __launch_bounds__(256) void tables_qn_kernel(Src src) {
-    extern __shared__ double pre[];
+__device__ inline void tables_qn_body(const Src& src, int blk, double* pre) {
     __shared__ double part_c[256], part_s[256];
     int p;
-    const TableJob T = src.get_q(blockIdx.x, p);
+    const TableJob T = src.get_q(blk, p);
     if (!(T.basis == B_FOURIER && T.hilbert == H_NODA)) return;
     const int64_t m = T.m;
     double* pc = pre;
@@ -317,6 +321,12 @@ __global__ __launch_bounds__(256) void tables_qn_kernel(Src src) {
             }
         }
     }
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void tables_qn_kernel(Src src) {
+    extern __shared__ double pre[];
+    tables_qn_body(src, blockIdx.x, pre);
 }
 
 // =========================================================================
@@ -476,11 +486,30 @@ __device__ inline void center_body(const PrepJob& J, int lb) {
 }
 
 template <class Src>
-__global__ __launch_bounds__(256) void center_kernel(Src src) {
+__device__ inline void center_dispatch(const Src& src, int blk) {
     int lb;
-    const PrepJob J = src.get(blockIdx.x, lb);
+    const PrepJob J = src.get(blk, lb);
     if (J.m <= 256) center_body<Src, true>(J, lb);
     else center_body<Src, false>(J, lb);
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void center_kernel(Src src) {
+    center_dispatch(src, blockIdx.x);
+}
+
+// The three preparation kernels of a single or heterocorrelation call on the
+// table-product path in one launch (they are independent of each other):
+// workgroups [0, nt) build the table, [nt, nt + nq) its Q N rows, the rest
+// centre the spectra.  Dynamic LDS: 32 m bytes (the table kernel's; the
+// Q N rows use the first 16 m).  Saves two launches per call, which is
+// what a small problem costs.
+__global__ __launch_bounds__(256) void prep_kernel(TableSrcInline ts, int nt, int nq, PrepSrcInline ps) {
+    extern __shared__ double prep_lds[];
+    const int b = blockIdx.x;
+    if (b < nt) tables_body(ts, b, prep_lds);
+    else if (b < nt + nq) tables_qn_body(ts, b - nt, prep_lds);
+    else center_dispatch(ps, b - nt - nq);
 }
 
 // =========================================================================
@@ -2001,6 +2030,11 @@ hipError_t launch_tables(const TableSrcInline& src, int blocks, int64_t max_m, h
 }
 hipError_t launch_tables(const TableSrcArray& src, int blocks, int64_t max_m, hipStream_t s) {
     hipLaunchKernelGGL(tables_kernel<TableSrcArray>, dim3(blocks), dim3(256), (size_t)(32 * max_m), s, src);
+    return hipGetLastError();
+}
+hipError_t launch_prep(const TableSrcInline& ts, int nt, int nq, int64_t m, const PrepSrcInline& ps, int nc,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(prep_kernel, dim3(nt + nq + nc), dim3(256), (size_t)(32 * m), s, ts, nt, nq, ps);
     return hipGetLastError();
 }
 hipError_t launch_center(const PrepSrcInline& src, int blocks, hipStream_t s) {

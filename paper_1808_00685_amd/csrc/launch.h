@@ -88,6 +88,11 @@ struct PrepSrcArray {
 hipError_t launch_tables(const TableSrcInline& src, int blocks, int64_t max_m, hipStream_t s);
 hipError_t launch_tables(const TableSrcArray& src, int blocks, int64_t max_m, hipStream_t s);
 hipError_t launch_center(const PrepSrcInline& src, int blocks, hipStream_t s);
+// tables (nt workgroups), their Q N rows (nq) and the centring (nc) in one
+// launch, for m <= kPrepMergeMaxM (its dynamic LDS is 32 m bytes)
+hipError_t launch_prep(const TableSrcInline& ts, int nt, int nq, int64_t m, const PrepSrcInline& ps, int nc,
+                       hipStream_t s);
+constexpr int64_t kPrepMergeMaxM = 1024;
 hipError_t launch_center(const PrepSrcArray& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s);
