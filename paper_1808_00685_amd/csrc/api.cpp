@@ -361,6 +361,21 @@ bool needs_qn(const corr2d_plan_s* p) {
     return p->d.basis == CORR2D_BASIS_FOURIER && p->d.hilbert == CORR2D_HILBERT_NODA;
 }
 
+// CORR2D_LOG set (and not "0") in the environment: one line per plan on
+// stderr with the decisions the library took.
+bool log_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("CORR2D_LOG");
+        return e && *e && std::strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+
+const char* prec_name(int prec) {
+    static const char* names[] = {"f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"};
+    return prec >= 0 && prec < 6 ? names[prec] : "?";
+}
+
 // Table-product plans with m <= kPrepMergeMaxM build the table and centre
 // the spectra in one launch (after the optional resampling); the others
 // launch their tables first (FFT plans centre inside the transform).
@@ -532,6 +547,14 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
         }
     }
     p->ws_bytes = off;
+    if (log_enabled())
+        std::fprintf(stderr,
+                     "corr2d: plan %s m=%lld n1=%lld n2=%lld layout=%d tile=%d (%dx%d) tiles=%lld "
+                     "transform=%s prep_launches=%d per_band_scale=%d workspace=%zu B tune: %s\n",
+                     prec_name(d->prec), (long long)d->m, (long long)d->n1, (long long)d->n2, d->out_layout,
+                     p->tile.id, 32 * p->tile.fm, 32 * p->tile.fn, (long long)p->ntiles,
+                     p->fft ? "radix FFT" : "DFT table product", p->fft ? 2 : (merged_prep(p) ? 2 : (needs_qn(p) ? 4 : 3)),
+                     (int)p->scale, p->ws_bytes, tune_source());
     *out = p;
     return ok();
 }
@@ -630,6 +653,15 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
     p->counter_off = off;
     off = align256(off + 256);
     p->ws_bytes = off;
+    if (log_enabled()) {
+        std::fprintf(stderr, "corr2d: batched plan %s items=%lld distinct_m=%zu tiles=%lld out_elements=%lld "
+                             "workspace=%zu B tune: %s\n",
+                     prec_name(common->prec), (long long)count, p->distinct_m.size(), (long long)p->total_tiles,
+                     (long long)p->out_elements, p->ws_bytes, tune_source());
+        for (const auto& gr : p->groups)
+            std::fprintf(stderr, "corr2d:   tile %d (%dx%d): %d data sets, %lld tiles, one persistent launch\n",
+                         gr.tile.id, 32 * gr.tile.fm, 32 * gr.tile.fn, gr.count, (long long)gr.tiles);
+    }
     *out = p;
     return ok();
 }

@@ -26,6 +26,7 @@ struct Rule {
 
 std::once_flag g_once;
 std::vector<Rule> g_rules;
+std::string g_source = "no table: size rule";
 
 std::string default_path() {
     Dl_info info;
@@ -55,9 +56,15 @@ void load() {
         }
     }
     std::fclose(f);
+    g_source = path + " (" + std::to_string(g_rules.size()) + " rules)";
 }
 
 }  // namespace
+
+const char* tune_source() {
+    std::call_once(g_once, load);
+    return g_source.c_str();
+}
 
 int tune_lookup(int prec, int64_t m, int64_t n) {
     std::call_once(g_once, load);

@@ -7,4 +7,7 @@ namespace corr2d {
 // size.  Reads the table named by CORR2D_TUNE_TABLE, else tune/gfx950.tsv
 // next to the library; without a table a size rule is used.
 int tune_lookup(int prec, int64_t m, int64_t n);
+// Where the rules came from (the table's path and rule count, or the size
+// rule), for the plan log.
+const char* tune_source();
 }

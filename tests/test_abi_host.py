@@ -214,6 +214,35 @@ def test_transform_selection(kw, fft):
     B.corr2d_plan_destroy(h)
 
 
+def test_plan_log():
+    """CORR2D_LOG=1: one stderr line per plan with the decisions taken (the
+    transform, tile and workspace); nothing without it."""
+    import subprocess
+    import sys
+    code = ("from paper_1808_00685_amd import binding as B\n"
+            "for kw in (dict(m=256, n1=16384, prec='split_bf16'), dict(m=11, n1=512, prec='f64')):\n"
+            "    _, h = B.corr2d_plan(B.corr2d_desc_init(**kw))\n"
+            "    B.corr2d_plan_destroy(h)\n"
+            "items = [B.corr2d_item(m=20, n=300), B.corr2d_item(m=128, n=700, out_offset=90000)]\n"
+            "_, h = B.corr2d_batched_plan(B.corr2d_desc_init(prec='f32'), items)\n"
+            "B.corr2d_plan_destroy(h)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CORR2D_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("corr2d:")]
+    assert "plan split_bf16 m=256 n1=16384" in lines[0] and "transform=radix FFT" in lines[0]
+    assert "plan f64 m=11 n1=512" in lines[1] and "transform=DFT table product" in lines[1]
+    assert "prep_launches=2" in lines[1] and "tune:" in lines[1]
+    assert "batched plan f32 items=2 distinct_m=2" in lines[2]
+    assert any("persistent launch" in ln for ln in lines[3:])
+    env["CORR2D_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0 and "corr2d:" not in r.stderr
+
+
 def test_compute_calls_reject_bad_arguments_before_device_work():
     d = B.corr2d_desc_init(m=11, n1=64)
     _, h = B.corr2d_plan(d)
