@@ -170,6 +170,9 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
         "kernel_ms": kernel_ms,
         "kernel_alg_tflops": alg_flops / (kernel_ms * 1e-3) / 1e12,
         "kernel_executed_tflops": executed / (kernel_ms * 1e-3) / 1e12,
+        # executed MFMA rate against the dense peak of the precision issued
+        "mfma_peak_tflops": PEAK_TFLOPS[prec],
+        "mfma_executed_frac": executed / (kernel_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
         "kernel_hbm_GBps": kernel_bytes / (kernel_ms * 1e-3) / 1e9,
         "err_phi": rel_fro(g_phi, oracle_vals[0]),
         "err_psi": rel_fro(g_psi, oracle_vals[1]),
@@ -519,7 +522,7 @@ def main():
                             "sampled_entries": int(len(sample[0]))},
         "cpu_baseline": cpu,
         "paper_context": paper_context(),
-        "variants": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()
+        "variants": [{k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in r.items()
                       if k not in ("alg_flops", "executed_flops", "kernel_bytes")}
                      for r in variants],
         "workloads": workloads,
