@@ -538,6 +538,30 @@ def test_fft_transform_hetero_ref_scaled(gpu):
     assert rel_fro(_np(psi), psi_o) <= TOL["split_bf16"]
 
 
+@pytest.mark.parametrize("prec", ["f64", "split_bf16"])
+def test_fft_transform_f32_input_stride_and_constant_column(gpu, prec):
+    """The fused centring reads FP32 input through a row stride larger than
+    n, and a constant column (zero variance) stays zero under scaling -- to
+    rounding: two spectral points share one complex FFT, and separating their
+    spectra leaves cross-talk at the transform's rounding level."""
+    import torch
+    m, n, ld = 256, 150, 170
+    S = _rand(m, n, 640)
+    S[:, 7] = 2.5
+    S32 = S.astype(np.float32)
+    big = np.zeros((m, ld), dtype=np.float32)
+    big[:, :n] = S32
+    y = torch.as_tensor(big, device=gpu)[:, :n]
+    for alpha in (0.0, 1.0):
+        phi_o, psi_o = oracle.corr2d(S32.astype(np.float64), alpha=alpha)
+        phi, psi, plan, _ = B.homo(y, prec=prec, alpha=alpha)
+        assert _transform(plan) == 1
+        ph, ps = _np(phi), _np(psi)
+        assert rel_fro(ph, phi_o) <= TOL[prec] and rel_fro(ps, psi_o) <= TOL[prec]
+        eps = (1e-14 if prec == "f64" else 1e-6) * np.abs(ph).max()
+        assert np.abs(ph[7]).max() <= eps and np.abs(ps[7]).max() <= eps
+
+
 def test_fft_transform_after_interpolation(gpu):
     m_in, m_out, n = 90, 128, 140
     t = _uneven(m_in, 610)
