@@ -821,13 +821,18 @@ template <int L> struct FftCfg {
 // (c, g) = (tid % PTS, tid / PTS) reads rows g + RG k of column p0 + c,
 // m = L/2 rows in all.  The column mean (or the caller's reference) and,
 // with a result scaling exponent alpha, sigma^-alpha are FP64 sums reduced
-// through LDS; the centred values (FP64, then rounded to float) stay in
-// registers (as float for the reduced formats); the column norm gives the
-// per-band scales, which go to s_sc and to the job's scale vectors (the
-// contraction reads them there).
+// through LDS; the column norm gives the per-band scales, which go to the
+// job's scale vectors (the contraction reads them there).  The centred
+// values enter the FFTs divided by a power of two 2^e near the column norm
+// (exact), and s_sc carries the operand scale times 2^e, which the emitted
+// rows are multiplied by: the two columns that share a complex FFT then
+// enter at unit norm, so the rounding-level cross-talk of their separation
+// stays relative to each column's own norm (a weak spectral variable next
+// to a strong one keeps its accuracy).  The values stay in registers (as
+// float for the reduced formats).
 template <int L, class S>
 __device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, S (&xf)[FftCfg<L>::MV],
-                                  float* s_sc, double* red) {
+                                  S* s_sc, double* red) {
     constexpr int PTS = FftCfg<L>::PTS, RG = FftCfg<L>::RG, MV = FftCfg<L>::MV;
     const int c = tid % PTS, g = tid / PTS;
     const int64_t col = p0 + c;
@@ -869,17 +874,22 @@ __device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, S (&xf)
     for (int k = 0; k < MV; ++k) {
         const double x = valid ? (v[k] - mean) * gsc : 0.0;
         nrm += x * x;
-        xf[k] = (S)x;
     }
     const double r = sqrt(colsum(nrm));
+    int e = 0;
+    if (r > 0.0) frexp(r, &e);   // r = f 2^e, f in [0.5, 1)
+    e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+    const double down = ldexp(1.0, -e);
+#pragma unroll
+    for (int k = 0; k < MV; ++k) xf[k] = (S)((valid ? (v[k] - mean) * gsc : 0.0) * down);
     if (g == 0) {
         float sa = 1.0f, sb = 1.0f;
         if (J.scale) {
             sa = pow2_scale(J.qhalf, J.boundA * r);
             sb = pow2_scale(J.qhalf, J.boundB * r);
         }
-        s_sc[c] = sa;
-        s_sc[PTS + c] = sb;
+        s_sc[c] = (S)ldexp((double)sa, e);
+        s_sc[PTS + c] = (S)ldexp((double)sb, e);
         if (J.sA) J.sA[col] = sa;
         if (J.sB) J.sB[col] = sb;
     }
@@ -1039,7 +1049,7 @@ template <int P> using FftS = typename std::conditional<P == P_F64, double, floa
 
 template <int P, int L>
 __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const FftV<P>* bufs, int off, int tid,
-                                bool isB, bool rot, bool zero_nyq, bool seq, const float* s_sc, int pt0) {
+                                bool isB, bool rot, bool zero_nyq, bool seq, const FftS<P>* s_sc, int pt0) {
     using V = FftV<P>;
     using S = FftS<P>;
     constexpr int M = L / 2, NP = 2 * FftCfg<L>::PW;
@@ -1067,7 +1077,7 @@ __device__ inline void fft_emit(const PrepJob& J, int64_t i0, const FftV<P>* buf
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = src[e];
     }
-    const float sc = s_sc[(isB ? FftCfg<L>::PTS : 0) + pt0 + pt];
+    const S sc = s_sc[(isB ? FftCfg<L>::PTS : 0) + pt0 + pt];
 #pragma unroll
     for (int e = 0; e < 8; ++e) x[e] *= sc;
     const int64_t i = i0 + pt, k = 8 * hb;
@@ -1082,7 +1092,7 @@ __global__ __launch_bounds__(256) void fft_transform_kernel(Src src) {
     using V = FftV<P>;
     using S = FftS<P>;
     __shared__ V s_buf[C::PW * C::PAIR];
-    __shared__ float s_sc[2 * C::PTS];
+    __shared__ S s_sc[2 * C::PTS];
     __shared__ double s_red[256];
     int lb;
     const PrepJob J = src.get(blockIdx.x, lb);

@@ -562,6 +562,27 @@ def test_fft_transform_f32_input_stride_and_constant_column(gpu, prec):
         assert np.abs(ph[7]).max() <= eps and np.abs(ps[7]).max() <= eps
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16"])
+def test_fft_transform_weak_columns_next_to_strong(gpu, prec):
+    """Every other spectral variable varies 1e5 times less than its FFT
+    partner: the block of weak variables must reach the tolerance on its
+    own, i.e. the separation of the paired spectra may not leak the strong
+    column's rounding into the weak one."""
+    m, n = 256, 96
+    rng = np.random.default_rng(650)
+    S = rng.standard_normal((m, n)) + 3.0
+    # no offset on the weak variables: with one, the FP64 mean's rounding
+    # (any summation order) would already move their Psi by ~1e-10
+    S[:, 1::2] = 1e-5 * rng.standard_normal((m, n // 2))
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, plan = _homo(S, gpu, prec=prec)
+    assert _transform(plan) == 1
+    w = np.arange(1, n, 2)
+    assert rel_fro(phi[np.ix_(w, w)], phi_o[np.ix_(w, w)]) <= TOL[prec]
+    assert rel_fro(psi[np.ix_(w, w)], psi_o[np.ix_(w, w)]) <= TOL[prec]
+    assert rel_fro(phi, phi_o) <= TOL[prec] and rel_fro(psi, psi_o) <= TOL[prec]
+
+
 def test_fft_transform_after_interpolation(gpu):
     m_in, m_out, n = 90, 128, 140
     t = _uneven(m_in, 610)
