@@ -628,6 +628,27 @@ def test_max_n_heterocorrelation(gpu):
     assert rel_fro(gq, qo) <= TOL["f32"]
 
 
+def test_fft_transform_large_n(gpu):
+    """The FFT transform (m = 128) over 2^22 spectral points: 64-bit offsets
+    in its loads, operand stores and scales; sampled entries, including the
+    last rows, against the oracle."""
+    m, n1, n2 = 128, 1 << 22, 5
+    rng = np.random.default_rng(530)
+    S1 = rng.standard_normal((m, n1)).astype(np.float32).astype(np.float64) + 1.0
+    S2 = rng.standard_normal((m, n2)) - 2.0
+    i = np.concatenate([rng.integers(0, n1, 2000), [n1 - 1, n1 - 2, n1 - 3, 0]])
+    j = np.concatenate([rng.integers(0, n2, 2000), [n2 - 1, 0, 3, 1]])
+    po, qo = oracle.corr2d_entries(S1, i, j, S2=S2)
+    phi, psi, plan, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), prec="split_bf16")
+    assert _transform(plan) == 1
+    import torch
+    idx = torch.as_tensor(i * n2 + j, device=gpu)
+    gp = phi.reshape(-1)[idx].double().cpu().numpy()
+    gq = psi.reshape(-1)[idx].double().cpu().numpy()
+    assert rel_fro(gp, po) <= TOL["split_bf16"]
+    assert rel_fro(gq, qo) <= TOL["split_bf16"]
+
+
 def test_wide_heterocorrelation(gpu):
     m, n1, n2 = 6, 120000, 37
     S1, S2 = _rand(m, n1, 510), _rand(m, n2, 511)
