@@ -629,8 +629,8 @@ def test_max_n_heterocorrelation(gpu):
 
 
 def test_fft_transform_large_n(gpu):
-    """The FFT transform (m = 128) over 2^22 spectral points: 64-bit offsets
-    in its loads, operand stores and scales; sampled entries, including the
+    """The FFT transform (m = 128) over 2^22 spectral points (262144
+    workgroups, operand planes of 2^30 bytes); sampled entries, including the
     last rows, against the oracle."""
     m, n1, n2 = 128, 1 << 22, 5
     rng = np.random.default_rng(530)
