@@ -150,9 +150,9 @@ typedef struct corr2d_desc {
     int32_t out_layout; /* corr2d_layout                                         */
     uint32_t flags;     /* CORR2D_FLAG_*                                         */
     int32_t tile;       /* 0 = automatic (tuned table); 1 = 64 x 64 output tiles
-                           (FP64, FP32, FP8); 2 = 128 x 128 (FP32, FP8) or
-                           256 x 128 (split-BF16, BF16, FP16); 3 = 128 x 128
-                           (split-BF16, BF16, FP16)                             */
+                           (FP64, FP32, FP8); 2 = 128 x 128 (FP32, FP8),
+                           128 x 64 (FP64) or 256 x 128 (split-BF16, BF16,
+                           FP16); 3 = 128 x 128 (split-BF16, BF16, FP16)       */
     int32_t reserved;
     double scale_alpha; /* exponent alpha of the result scaling: Phi and Psi
                            divided by (sigma_1 sigma_2)^alpha, Sec. 2 Eqs.

@@ -101,14 +101,16 @@ struct Tile {
     int id = 2, fm = 4, fn = 4;
 };
 
-// Tile id 1: 64 x 64 outputs; id 2: 128 x 128, or 256 x 128 for the 16-bit
-// formats (LDS-staged kernel, one workgroup per CU); id 3: 128 x 128 of the
+// Tile id 1: 64 x 64 outputs; id 2: 128 x 128, 128 x 64 for FP64 (its
+// accumulators are twice as wide), or 256 x 128 for the 16-bit formats
+// (LDS-staged kernel, one workgroup per CU); id 3: 128 x 128 of the
 // LDS-staged kernel (two workgroups per CU).
 Tile tile_from_id(int id, int prec) {
     Tile t;
     t.id = id;
     t.fm = t.fn = (id == 1) ? 2 : 4;
     if (id == 2 && blocked_layout(prec)) t.fm = 8;
+    if (id == 2 && prec == CORR2D_PREC_F64) t.fn = 2;   // FP64: 128 x 64
     return t;
 }
 
@@ -217,8 +219,6 @@ corr2d_status check_common(const corr2d_desc* d) {
         return fail(CORR2D_EINVAL, "unknown tile id %d", d->tile);
     if (d->tile == 3 && !blocked_layout(d->prec))
         return fail(CORR2D_EUNSUPPORTED, "tile 3 (128x128, LDS-staged) is built for the 16-bit formats only");
-    if (d->tile == 2 && d->prec == CORR2D_PREC_F64)
-        return fail(CORR2D_EUNSUPPORTED, "tile 2 (128x128) is not built for FP64");
     if (d->tile == 1 && blocked_layout(d->prec))
         return fail(CORR2D_EUNSUPPORTED, "tile 1 (64x64) is not built for the 16-bit formats");
     return CORR2D_OK;

@@ -2105,7 +2105,7 @@ hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipSt
     return launch_transform_t(prec, src, blocks, s);
 }
 
-#define CORR_CASES(X) X(P_F64, 2, 2) X(P_F32, 4, 4) X(P_FP8, 4, 4) X(P_F32, 2, 2) X(P_FP8, 2, 2)
+#define CORR_CASES(X) X(P_F64, 2, 2) X(P_F64, 4, 2) X(P_F32, 4, 4) X(P_FP8, 4, 4) X(P_F32, 2, 2) X(P_FP8, 2, 2)
 #define CORR2_CASES(X) X(P_SPLIT) X(P_BF16) X(P_F16)
 
 hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s) {

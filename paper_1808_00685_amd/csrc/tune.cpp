@@ -70,7 +70,7 @@ int tune_lookup(int prec, int64_t m, int64_t n) {
     std::call_once(g_once, load);
     for (const Rule& r : g_rules)
         if (r.prec == prec && m <= r.m_max && n <= r.n_max) {
-            if (prec == P_F64 && r.tile != 1) continue;
+            if (prec == P_F64 && r.tile != 1 && r.tile != 2) continue;
             if (blocked_layout(prec) && r.tile != 2 && r.tile != 3) continue;
             if (!blocked_layout(prec) && r.tile == 3) continue;
             return r.tile;

@@ -25,7 +25,7 @@ OPEN = 1 << 40   # upper bound of the last size class
 # tile ids built per precision (1: 64 x 64, 2: 128 x 128 or 256 x 128 for the
 # 16-bit formats, 3: 128 x 128 of the LDS-staged kernel)
 CANDIDATES = {
-    "f64": [1],
+    "f64": [1, 2],
     "f32": [1, 2],
     "split_bf16": [2, 3],
     "bf16": [2, 3],

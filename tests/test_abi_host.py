@@ -127,7 +127,7 @@ def _plan_status(**kw):
     (dict(flags=0x20), B.EINVAL),
     (dict(flags=B.FLAG_TRANSFORM_MATMUL), B.OK),
     (dict(tile=7), B.EINVAL),
-    (dict(prec=0, tile=2), B.EUNSUPPORTED),
+    (dict(prec=0, tile=2), B.OK),
     (dict(prec=1, tile=3), B.EUNSUPPORTED),
     (dict(prec=2, tile=3), B.OK),
     (dict(scale_alpha=float("nan")), B.EINVAL),

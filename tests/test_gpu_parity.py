@@ -156,7 +156,7 @@ def _homo_nan_filled(S, dev, **kw):
     return _np(phi), _np(psi), plan
 
 
-@pytest.mark.parametrize("prec,tile", [("f64", 1), ("f32", 1), ("f32", 2), ("fp8_e4m3", 1),
+@pytest.mark.parametrize("prec,tile", [("f64", 1), ("f64", 2), ("f32", 1), ("f32", 2), ("fp8_e4m3", 1),
                                        ("fp8_e4m3", 2), ("split_bf16", 2), ("split_bf16", 3),
                                        ("bf16", 3), ("f16", 2)])
 @pytest.mark.parametrize("n", [1, 33, 333])
@@ -260,6 +260,34 @@ def test_lds_staged_tile_shapes(gpu, prec, tile, layout):
     phi, psi, _, _ = B.hetero(_t(S, gpu), _t(S2, gpu), prec=prec, tile=tile)
     assert rel_fro(_np(phi), phi_o) <= TOL[prec]
     assert rel_fro(_np(psi), psi_o) <= TOL[prec]
+
+
+@pytest.mark.parametrize("layout", ["full", "upper_packed", "upper_aligned"])
+def test_f64_128x64_tile(gpu, layout):
+    """FP64's tile 2 (128 x 64: row tiles twice as tall as column tiles) in
+    every layout with ragged edges and diagonal-crossing tiles, and for a
+    heterocorrelation; bit-identical to the 64 x 64 tile (each element sums
+    its K terms in the same order)."""
+    m, n = 37, 700
+    S = _rand(m, n, 79)
+    phi_o, psi_o = oracle.corr2d(S)
+    phi, psi, plan = _homo_nan_filled(S, gpu, prec="f64", tile=2, out_layout=layout)
+    assert (plan.info.tile_m, plan.info.tile_n) == (128, 64)
+    ref = _homo_nan_filled(S, gpu, prec="f64", tile=1, out_layout=layout)
+    assert np.array_equal(np.nan_to_num(phi, nan=7.0), np.nan_to_num(ref[0], nan=7.0))
+    assert np.array_equal(np.nan_to_num(psi, nan=7.0), np.nan_to_num(ref[1], nan=7.0))
+    if layout == "full":
+        P, Q = phi.reshape(n, n), psi.reshape(n, n)
+    elif layout == "upper_packed":
+        P, Q = unpack_upper(phi, n), unpack_upper(psi, n)
+    else:
+        P, Q = unpack_upper_aligned(phi, n)[0], unpack_upper_aligned(psi, n)[0]
+    iu = np.triu_indices(n)
+    assert rel_fro(P[iu], phi_o[iu]) <= TOL["f64"] and rel_fro(Q[iu], psi_o[iu]) <= TOL["f64"]
+    S2 = _rand(m, 300, 80)
+    phi_o, psi_o = oracle.corr2d(S, S2)
+    phi, psi, _, _ = B.hetero(_t(S, gpu), _t(S2, gpu), prec="f64", tile=2)
+    assert rel_fro(_np(phi), phi_o) <= TOL["f64"] and rel_fro(_np(psi), psi_o) <= TOL["f64"]
 
 
 # --------------------------------------------------------------------------
