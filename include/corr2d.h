@@ -212,6 +212,15 @@ typedef struct corr2d_plan_info {
     int32_t transform;    /* perturbation-axis transform: 0 = product with the DFT
                              table on MFMA, 1 = radix FFT in LDS                  */
     int32_t reserved;
+    /* Single and hetero plans: byte offsets in the workspace of the reference
+     * spectra a call subtracts (Sec. 2 Eqs. (dynspec), (ref); the Ref1 and
+     * Ref2 of the paper's result object, Sec. 3): n1 (n2) doubles, the
+     * perturbation mean computed in FP64, or a copy of the caller's ref1
+     * (ref2).  Written by every call, readable once it has completed, until
+     * the workspace is used again.  Homocorrelation: ref2_offset equals
+     * ref1_offset.  Batched plans: 0 (not reported).                         */
+    size_t ref1_offset;
+    size_t ref2_offset;
 } corr2d_plan_info;
 
 /* Fill *d with defaults: FP64 input, FP32 output, SPLIT_BF16, FOURIER, NODA
@@ -235,8 +244,8 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
 corr2d_status corr2d_plan_destroy(corr2d_plan_t plan);
 
 /* Device workspace a call needs, in bytes (the caller allocates it; 256-byte
- * alignment required).  It holds the transform tables, the centred spectra,
- * the packed contraction operands and scale vectors.                         */
+ * alignment required).  It holds the transform tables, the reference and
+ * centred spectra, the packed contraction operands and scale vectors.        */
 corr2d_status corr2d_workspace_bytes(corr2d_plan_t plan, size_t* bytes);
 
 corr2d_status corr2d_plan_get_info(corr2d_plan_t plan, corr2d_plan_info* info);

@@ -64,6 +64,7 @@ class corr2d_plan_info(ctypes.Structure):
         ("per_band_scale", ctypes.c_int32), ("c", ctypes.c_double),
         ("workspace_bytes", ctypes.c_size_t), ("items", ctypes.c_int64),
         ("out_elements", ctypes.c_int64), ("transform", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("ref1_offset", ctypes.c_size_t), ("ref2_offset", ctypes.c_size_t),
     ]
 
 
@@ -338,7 +339,8 @@ def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basi
     import torch
     m, n1 = y1.shape
     m2, n2 = y2.shape
-    assert m == m2
+    if m != m2:
+        raise ValueError(f"y1 has {m} perturbation steps and y2 {m2}: both sets need the same")
     if interp != "none":
         m = m_out or m
     if out_dtype is None:
@@ -354,3 +356,64 @@ def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basi
     ws = plan.workspace(y1.device)
     corr2d_hetero(plan.handle, y1, ref1, y2, ref2, phi, psi, ws, stream=stream)
     return phi, psi, plan, ws
+
+
+def workspace_vector(ws, offset, n):
+    """The n doubles at byte offset `offset` of the workspace tensor ws, as a
+    float64 view (no copy, no device work)."""
+    import torch
+    return ws[offset:offset + 8 * n].view(torch.float64)
+
+
+class Corr2D:
+    """What the paper's corr2d() returns (Sec. 3), over device tensors:
+
+    phi, psi    synchronous and asynchronous spectra, in the plan's layout
+                (n1 x n2 for the full layout, else one packed triangle)
+    ft          phi + i psi as one complex tensor (built on first access)
+    ref1, ref2  the reference spectra the call subtracted: the perturbation
+                means computed by the centring kernels in FP64, or the
+                caller's references (float64 views of the workspace)
+    wave1, wave2  the spectral axes given by the caller, else 0 .. n - 1
+    plan, ws    the plan and the workspace the views above live in
+    """
+
+    def __init__(self, phi, psi, ref1, ref2, wave1, wave2, plan, ws):
+        self.phi, self.psi = phi, psi
+        self.ref1, self.ref2 = ref1, ref2
+        self.wave1, self.wave2 = wave1, wave2
+        self.plan, self.ws = plan, ws
+        self._ft = None
+
+    @property
+    def ft(self):
+        if self._ft is None:
+            import torch
+            self._ft = torch.complex(self.phi, self.psi)
+        return self._ft
+
+
+def corr2d(y1, y2=None, ref1=None, ref2=None, wave1=None, wave2=None, layout="full", **kw):
+    """The paper's corr2d() (Sec. 3): the homocorrelation of y1 (m x n1, on
+    the GPU), or with y2 (m x n2) the heterocorrelation; ref1 / ref2 replace
+    the perturbation means (Eq. (dynspec)).  The other keywords are those of
+    homo() and hetero() (prec, basis, hilbert, norm, alpha, interp, ...).
+    Asynchronous on the stream like them; returns a Corr2D."""
+    import torch
+    n1 = y1.shape[1]
+    if y2 is None:
+        if ref2 is not None or wave2 is not None:
+            raise ValueError("ref2 and wave2 belong to a heterocorrelation (give y2)")
+        phi, psi, plan, ws = homo(y1, ref=ref1, layout=layout, **kw)
+        n2 = n1
+    else:
+        if layout != "full":
+            raise ValueError("a heterocorrelation has the full layout only")
+        phi, psi, plan, ws = hetero(y1, y2, ref1=ref1, ref2=ref2, **kw)
+        n2 = y2.shape[1]
+    info = plan.info
+    r1 = workspace_vector(ws, info.ref1_offset, n1)
+    r2 = r1 if y2 is None else workspace_vector(ws, info.ref2_offset, n2)
+    w1 = wave1 if wave1 is not None else torch.arange(n1, dtype=torch.float64)
+    w2 = wave2 if wave2 is not None else (w1 if y2 is None else torch.arange(n2, dtype=torch.float64))
+    return Corr2D(phi, psi, r1, r2, w1, w2, plan, ws)

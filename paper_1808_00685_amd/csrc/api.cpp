@@ -93,7 +93,7 @@ Geo geometry(int64_t m, int64_t n, int prec) {
 
 // Workspace regions of one data set (byte offsets from the workspace base).
 struct SetLayout {
-    size_t yt = 0, sA = 0, sB = 0, A0 = 0, A1 = 0, B0 = 0, B1 = 0;
+    size_t ref = 0, yt = 0, sA = 0, sB = 0, A0 = 0, A1 = 0, B0 = 0, B1 = 0;
     bool has_b = false;
 };
 
@@ -262,6 +262,7 @@ SetLayout layout_set(const Geo& g, int prec, bool t64, bool need_b, size_t* off)
     const size_t tsz = t64 ? 8 : 4;
     const size_t esz = (size_t)elem_bytes(prec);
     const size_t plane = (size_t)g.n_pad * g.kp * esz;
+    s.ref = *off; *off = align256(*off + (size_t)g.n_pad * sizeof(double));
     s.yt = *off; *off = align256(*off + (size_t)g.n_pad * g.kt * tsz);
     s.sA = *off; *off = align256(*off + (size_t)g.n_pad * 4);
     s.A0 = *off; *off = align256(*off + plane);
@@ -328,6 +329,7 @@ PrepJob make_prep_job(const corr2d_plan_s* p, const Geo& g, const SetLayout& s, 
     j.alpha = p->d.scale_alpha;
     j.hilbert = p->d.hilbert;
     j.basis = p->d.basis;
+    j.ref_out = at<double>(ws, s.ref);
     return j;
 }
 
@@ -709,6 +711,8 @@ corr2d_status corr2d_plan_get_info(corr2d_plan_t p, corr2d_plan_info* info) {
         info->tiles = p->ntiles;
         info->c = p->c;
         info->transform = p->fft ? 1 : 0;
+        info->ref1_offset = p->s1.ref;
+        info->ref2_offset = p->hetero ? p->s2.ref : p->s1.ref;
     }
     return ok();
 }

@@ -83,6 +83,8 @@ struct PrepJob {
     double alpha;         // result scaling exponent (0: none): columns x sigma^-alpha
     int32_t hilbert;      // Hilbert and Basis (the radix FFT transform builds
     int32_t basis;        // the operands from them, without a table)
+    double* ref_out;      // n doubles (workspace): the reference spectrum the
+                          // centring subtracted (the mean, or a copy of ref)
 };
 
 // Resampling of one data set onto the equidistant perturbation grid: out =

@@ -399,6 +399,7 @@ __device__ inline void center_body(const PrepJob& J, int lb) {
         mean = t / (double)J.m;
         __syncthreads();
     }
+    if (g == 0 && valid && J.ref_out) J.ref_out[col] = mean;
 
     double gsc = 1.0;   // sigma^-alpha of this column
     if (J.alpha != 0.0) {
@@ -892,6 +893,7 @@ __device__ inline void fft_center(const PrepJob& J, int64_t p0, int tid, S (&xf)
         s_sc[PTS + c] = (S)ldexp((double)sb, e);
         if (J.sA) J.sA[col] = sa;
         if (J.sB) J.sB[col] = sb;
+        if (valid && J.ref_out) J.ref_out[col] = mean;
     }
 }
 

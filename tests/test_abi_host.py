@@ -67,10 +67,10 @@ def test_struct_layout_matches_binding():
 #include <stddef.h>
 #include "corr2d.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(corr2d_desc), offsetof(corr2d_desc, norm_value),
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(corr2d_desc), offsetof(corr2d_desc, norm_value),
         offsetof(corr2d_desc, tile), offsetof(corr2d_desc, scale_alpha),
         offsetof(corr2d_desc, t_in), offsetof(corr2d_desc, interp), sizeof(corr2d_item),
-        sizeof(corr2d_plan_info));
+        sizeof(corr2d_plan_info), offsetof(corr2d_plan_info, ref1_offset));
  return 0;}
 '''
     import tempfile
@@ -83,7 +83,8 @@ int main(void){
     assert vals == [ctypes.sizeof(B.corr2d_desc), B.corr2d_desc.norm_value.offset,
                     B.corr2d_desc.tile.offset, B.corr2d_desc.scale_alpha.offset,
                     B.corr2d_desc.t_in.offset, B.corr2d_desc.interp.offset,
-                    ctypes.sizeof(B.corr2d_item), ctypes.sizeof(B.corr2d_plan_info)]
+                    ctypes.sizeof(B.corr2d_item), ctypes.sizeof(B.corr2d_plan_info),
+                    B.corr2d_plan_info.ref1_offset.offset]
 
 
 def test_defaults():
@@ -191,6 +192,30 @@ def test_plan_info():
     _, h = B.corr2d_plan(d)
     import math
     assert B.corr2d_plan_get_info(h).c == pytest.approx(10 / (math.pi * 9))
+    B.corr2d_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw", [dict(m=11, n1=512), dict(m=256, n1=1000, prec="f64"),
+                                dict(m=64, n1=300, n2=700, prec="f32"),
+                                dict(m=16, n1=300, interp="linear", t_in=np.linspace(0.0, 1.0, 9))])
+def test_plan_info_reference_offsets(kw):
+    """The reference spectra (n1, n2 doubles) lie inside the workspace,
+    256-byte aligned, apart from each other; a homocorrelation has one."""
+    _, h = B.corr2d_plan(B.corr2d_desc_init(**kw))
+    info = B.corr2d_plan_get_info(h)
+    ws = B.corr2d_workspace_bytes(h)
+    n1, n2 = kw["n1"], kw.get("n2", 0)
+    assert info.ref1_offset % 256 == 0 and info.ref1_offset + 8 * n1 <= ws
+    if n2:
+        assert info.ref2_offset % 256 == 0 and info.ref2_offset + 8 * n2 <= ws
+        lo, hi = sorted([(info.ref1_offset, n1), (info.ref2_offset, n2)])
+        assert lo[0] + 8 * lo[1] <= hi[0]
+    else:
+        assert info.ref2_offset == info.ref1_offset
+    B.corr2d_plan_destroy(h)
+    _, h = B.corr2d_batched_plan(B.corr2d_desc_init(prec="f32"), [(11, 300, 0, 0, 0)])
+    info = B.corr2d_plan_get_info(h)
+    assert info.ref1_offset == 0 and info.ref2_offset == 0
     B.corr2d_plan_destroy(h)
 
 

@@ -450,6 +450,98 @@ def test_r_compat_hetero_and_scaled(gpu):
 # --------------------------------------------------------------------------
 # Interpolation to equidistant perturbation values (Sec. 4.1)
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# The result object of Sec. 3: reference spectra, complex FT, spectral axes
+# --------------------------------------------------------------------------
+def _mean_tol(m, S):
+    # an m-term FP64 sum in another order than the oracle's
+    return 4 * m * 2.0 ** -52 * float(np.abs(S).max())
+
+
+@pytest.mark.parametrize("prec,m,n,in32", [("f64", 11, 512, False), ("f32", 64, 300, True),
+                                           ("split_bf16", 256, 129, False), ("fp8_e4m3", 128, 70, False),
+                                           ("f64", 1024, 33, True), ("bf16", 2, 1, False)])
+def test_reference_spectrum_is_the_mean(gpu, prec, m, n, in32):
+    """The perturbation mean each call subtracts (Eq. (ref)), from the
+    table-product path's centring kernel and from the FFT kernel's fused
+    centring, equals the oracle's FP64 mean; ft is phi + i psi."""
+    import torch
+    S = _rand(m, n, 700 + m)
+    if in32:
+        S = S.astype(np.float32).astype(np.float64)
+    y = _t(S, gpu, torch.float32 if in32 else torch.float64)
+    r = B.corr2d(y, prec=prec)
+    assert r.plan.info.transform == (1 if m in (128, 256, 1024) else 0)
+    _, mean_o = oracle.dynamic(S)
+    ref1 = _np(r.ref1)
+    assert ref1.shape == (n,)
+    assert np.abs(ref1 - mean_o).max() <= _mean_tol(m, S)
+    assert r.ref2 is r.ref1
+    assert torch.equal(r.ft.real, r.phi) and torch.equal(r.ft.imag, r.psi)
+    assert np.array_equal(r.wave1.numpy(), np.arange(n)) and r.wave2 is r.wave1
+    phi_o, psi_o = oracle.corr2d(S)
+    assert rel_fro(_np(r.phi), phi_o) <= TOL[prec]
+    assert rel_fro(_np(r.psi), psi_o) <= TOL[prec]
+
+
+@pytest.mark.parametrize("m", [32, 256])
+def test_reference_spectra_hetero_given_and_mean(gpu, m):
+    """Heterocorrelation with a caller's ref1 and the mean for set 2: Ref1
+    is the caller's spectrum bit for bit, Ref2 the mean of y2; the spectral
+    axes are passed through."""
+    import torch
+    n1, n2 = 150, 90
+    S1, S2 = _rand(m, n1, 710), _rand(m, n2, 711) * 5.0
+    r1 = S1[3] - 0.25
+    w1 = torch.linspace(1600.0, 1500.0, n1, dtype=torch.float64)
+    r = B.corr2d(_t(S1, gpu), _t(S2, gpu), ref1=_t(r1, gpu), wave1=w1, prec="f32")
+    assert np.array_equal(_np(r.ref1), r1)
+    _, mean2 = oracle.dynamic(S2)
+    assert np.abs(_np(r.ref2) - mean2).max() <= _mean_tol(m, S2)
+    assert r.wave1 is w1 and np.array_equal(r.wave2.numpy(), np.arange(n2))
+    phi_o, psi_o = oracle.corr2d(S1, S2, ref1=r1)
+    assert rel_fro(_np(r.phi), phi_o) <= TOL["f32"]
+    assert rel_fro(_np(r.psi), psi_o) <= TOL["f32"]
+    assert tuple(r.ft.shape) == (n1, n2)
+
+
+@pytest.mark.parametrize("m_out", [40, 128])
+def test_reference_spectrum_after_interpolation(gpu, m_out):
+    """With interpolation the mean is taken over the resampled spectra."""
+    m_in, n = 23, 140
+    t = _uneven(m_in, 720)
+    S = _rand(m_in, n, 721)
+    Si = oracle.interpolate(S, t, m_out, "spline")
+    r = B.corr2d(_t(S, gpu), prec="split_bf16", interp="spline", t_in=t, m_out=m_out)
+    _, mean_o = oracle.dynamic(Si)
+    assert np.abs(_np(r.ref1) - mean_o).max() <= 1e-12 * float(np.abs(Si).max())
+
+
+def test_reference_spectrum_follows_each_call(gpu):
+    """A second call on the same plan and workspace rewrites the reference."""
+    import torch
+    m, n = 64, 200
+    S1, S2 = _rand(m, n, 730), _rand(m, n, 731) - 7.0
+    plan = B.Plan(m=m, n1=n, prec="f32")
+    ws = plan.workspace(gpu)
+    phi = torch.empty(n * n, dtype=torch.float32, device=gpu)
+    psi = torch.empty_like(phi)
+    for S in (S1, S2):
+        B.corr2d_homo(plan.handle, _t(S, gpu), None, phi, psi, ws)
+        got = _np(B.workspace_vector(ws, plan.info.ref1_offset, n))
+        assert np.abs(got - oracle.dynamic(S)[1]).max() <= _mean_tol(m, S)
+
+
+def test_corr2d_bundle_rejects_mixed_arguments(gpu):
+    y = _t(_rand(8, 10, 740), gpu)
+    with pytest.raises(ValueError):
+        B.corr2d(y, ref2=y[0])
+    with pytest.raises(ValueError):
+        B.corr2d(y, y, layout="upper_packed")
+    with pytest.raises(ValueError):
+        B.hetero(y, _t(_rand(9, 10, 741), gpu))
+
+
 def _uneven(m_in, seed):
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.uniform(0.3, 2.5, size=m_in))
