@@ -1342,6 +1342,13 @@ __device__ inline void put4(OT* o, int64_t idx, V4<OT> v) {
     }
 }
 
+// One output element: the row exponent applied in the output type, and a
+// non-temporal store for FP32 (as in put4).
+__device__ inline float unscale1(float v, int e) { return ldexpf(v, e); }
+__device__ inline double unscale1(double v, int e) { return ldexp(v, e); }
+__device__ inline void put1(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ inline void put1(double* p, double v) { *p = v; }
+
 // Exponents that undo the power-of-two operand scales of one TM x TN output
 // tile, gathered once per tile into an LDS table for the epilogue:
 // [0, TM) the left rows i0 + r, [TM, TM + TN) the right A columns j0 + c,
@@ -1505,7 +1512,8 @@ __host__ __device__ constexpr int corr_lds_bytes(int fm, int fn, bool out_f64) {
 }
 
 // One output tile (I, J) of size (32 FM) x (32 FN) computed by 4 waves (2x2)
-// with register-direct fragments, then written through LDS.
+// with register-direct fragments, then written through LDS (FP64 interior
+// tiles: straight from the accumulators).
 template <int P, int FM, int FN>
 __device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds, int* sexp) {
     using FT = typename Frag<P>::T;
@@ -1571,7 +1579,52 @@ __device__ inline void corr_tile(const CorrJob& C, int I, int J, char* lds, int*
     se.store(sexp, tid);
     auto stage = [&](auto* T, AT (&acc)[FM][FN], bool psi) {
         using OT = typename std::remove_pointer<decltype(T)>::type;
-        lds_barrier();   // previous readers of the LDS are done
+        lds_barrier();   // previous readers of the LDS are done (and the scale table is visible)
+        if constexpr (P == P_F64) {
+            // Interior tiles of the FP64 path store straight from the
+            // accumulators: register q of a 16 x 16 block holds row kg + 4q
+            // and column row16, so each store writes 16 consecutive doubles
+            // (one 128-byte line) of four rows, and the mirror of the full
+            // layout takes the transposed element.  The rounding is that of
+            // the staged path (scale in FP64, then the row exponent), so the
+            // results are the same bit for bit.  The FP32-accumulator formats
+            // keep the staged path: their register rows are 64-byte halves
+            // of a line, slower than the staged full-row stores.
+            if (ti0 + BM <= C.n1 && tj0 + BN <= C.n2 && !diag) {
+                OT* out = (OT*)(psi ? C.psi : C.phi);
+                const bool full = !C.homo || C.layout == L_FULL;
+                const bool mirror = C.homo && C.layout == L_FULL;
+                auto rowoff = [&](int64_t i) -> int64_t {
+                    return full ? i * C.ld_out
+                                : (C.layout == L_UPPER ? packed_row_base(i, C.n1) : aligned_row_base(i, C.n1));
+                };
+                const OT sg = psi ? OT(-1) : OT(1);
+#pragma unroll
+                for (int a = 0; a < FM; ++a) {
+                    int il[4];
+                    int64_t ro[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        il[q] = (int)(i0 - ti0) + a * 16 + kg + 4 * q;
+                        ro[q] = rowoff(ti0 + il[q]);
+                    }
+                    const int e[4] = {sexp[il[0]], sexp[il[1]], sexp[il[2]], sexp[il[3]]};
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) {
+                        const int jl = (int)(j0 - tj0) + b * 16 + row16;
+                        const double fc = ldexp(C.c, sexp[BM + (psi ? BN : 0) + jl]);
+                        const int64_t j = tj0 + jl;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const OT v = unscale1((OT)((double)acc[a][b][q] * fc), e[q]);
+                            put1(out + ro[q] + j, v);
+                            if (mirror) put1(out + j * C.ld_out + ti0 + il[q], sg * v);
+                        }
+                    }
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
             const int jl = (int)(j0 - tj0) + b * 16 + row16;

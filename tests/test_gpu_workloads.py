@@ -11,6 +11,7 @@ from paper_1808_00685_amd import binding as B
 from paper_1808_00685_amd import synth
 
 from .gpu_helpers import BF16_BAND_TOL, TOL, packed_index, rel_fro
+from .lag_pairs import lag_sign_pairs
 
 pytestmark = pytest.mark.gpu
 
@@ -140,6 +141,10 @@ def test_hetero_workload_sampled(gpu, hetero_data, prec):
     sel = slice(len(i) - ncoupled, len(i))
     big = np.abs(psi_o[sel]) > 0.05 * np.abs(psi_o[sel]).max()
     assert np.all(np.sign(g_psi[sel][big]) == np.sign(psi_o[sel][big]))
+    # and with the generator's driver lags where those fix it
+    li, lj, expected = lag_sign_pairs(meta)
+    lag = psi[torch.as_tensor(li, device=gpu), torch.as_tensor(lj, device=gpu)].double().cpu().numpy()
+    assert np.all(np.sign(lag) == expected)
 
 
 def _batch(count, seed, n_range):
