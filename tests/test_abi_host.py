@@ -371,3 +371,18 @@ def test_batched_out_elements_upper_aligned():
     _, h = B.corr2d_batched_plan(d, items)
     assert B.corr2d_plan_get_info(h).out_elements == e300 + B.upper_aligned_elements(1000)
     B.corr2d_plan_destroy(h)
+
+
+def test_result_object_argument_errors_before_any_call():
+    """corr2d() and hetero() reject inconsistent arguments before a plan is
+    made or any device memory is touched (CPU tensors suffice)."""
+    import torch
+    y = torch.zeros(8, 10, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        B.corr2d(y, ref2=y[0])
+    with pytest.raises(ValueError):
+        B.corr2d(y, wave2=torch.arange(10.0))
+    with pytest.raises(ValueError):
+        B.corr2d(y, y, layout="upper_aligned")
+    with pytest.raises(ValueError):
+        B.hetero(y, torch.zeros(9, 10, dtype=torch.float64))
