@@ -1735,19 +1735,27 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
     const int64_t i0 = (int64_t)I * TM, j0 = (int64_t)J * kTileN2;
     const bool diag = C.homo && j0 <= i0 + TM - 1;
     lds_barrier();   // previous readers of the LDS are done (and the scale table is visible)
-    if (C.homo && C.layout == L_UPPER_ALIGNED && i0 + TM <= C.n1 && j0 + kTileN2 <= C.n2 && !diag) {
-        // Row-aligned upper layout, interior tile: straight from the
-        // accumulators.  Register r of a 32 x 32 block holds 32 consecutive
-        // columns of two rows, whole aligned 128-byte lines here, so no
-        // staging through LDS is needed.  The block's 32 rows lie in one
-        // 32-row band of the layout and share its row length.  Non-temporal
-        // stores, as in put4.
+    const bool interior = i0 + TM <= C.n1 && j0 + kTileN2 <= C.n2;
+    // A heterocorrelation (full layout, no mirror) takes the direct path
+    // below when its rows are whole 128-byte lines: row stride a multiple of
+    // 32 floats below 2^31, output 128-byte aligned.
+    const bool hfull = !C.homo && interior && (C.ld_out & 31) == 0 && C.ld_out < (int64_t(1) << 31) &&
+                       ((uintptr_t)(psi ? C.psi : C.phi) & 127) == 0;
+    if ((C.homo && C.layout == L_UPPER_ALIGNED && interior && !diag) || hfull) {
+        // Row-aligned upper layout (or the heterocorrelation above), interior
+        // tile: straight from the accumulators.  Register r of a 32 x 32 block
+        // holds 32 consecutive columns of two rows, whole aligned 128-byte
+        // lines here, so no staging through LDS is needed.  The block's 32
+        // rows lie in one 32-row band of the upper layout and share its row
+        // length (the row stride for the full layout).  Non-temporal stores,
+        // as in put4.
         float* out = (float*)(psi ? C.psi : C.phi);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const int64_t ia = i0 + wi * 64 + a * 32;
-            const int64_t base = aligned_row_base(ia, C.n1);
-            const uint32_t len = (((uint32_t)C.n1 + 31u) & ~31u) - 32u * (uint32_t)(ia >> 5);
+            const int64_t base = hfull ? ia * C.ld_out : aligned_row_base(ia, C.n1);
+            const uint32_t len = hfull ? (uint32_t)C.ld_out
+                                       : (((uint32_t)C.n1 + 31u) & ~31u) - 32u * (uint32_t)(ia >> 5);
             int4 re[4];   // row exponents of rows ia + 8k + 4g .. + 3
 #pragma unroll
             for (int k = 0; k < 4; ++k) re[k] = *(const int4*)(sexp + wi * 64 + a * 32 + 8 * k + 4 * g);

@@ -304,6 +304,34 @@ def test_hetero_parity(gpu, prec, m, n1, n2):
     assert rel_fro(_np(psi), psi_o) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
+def test_hetero_direct_and_staged_stores_agree(gpu, prec):
+    """Interior tiles of a heterocorrelation are stored straight from the
+    accumulators when every output row is whole 128-byte lines (row stride
+    a multiple of 32, aligned output), else through LDS: the three calls
+    below (aligned; output shifted by one element; row stride n2 + 1) give
+    the same bits, and match the oracle."""
+    import torch
+    m, n1, n2 = 64, 384, 256
+    S1, S2 = _rand(m, n1, 750), _rand(m, n2, 751)
+    y1, y2 = _t(S1, gpu), _t(S2, gpu)
+    got = []
+    for shift, ld in ((0, n2), (1, n2), (0, n2 + 1)):
+        plan = B.Plan(m=m, n1=n1, n2=n2, prec=prec, ld_out=ld)
+        ws = plan.workspace(gpu)
+        bufs = [torch.full((n1 * ld + shift,), float("nan"), dtype=torch.float32, device=gpu)
+                for _ in range(2)]
+        phi, psi = (b[shift:] for b in bufs)
+        B.corr2d_hetero(plan.handle, y1, None, y2, None, phi, psi, ws)
+        torch.cuda.synchronize()
+        got.append(tuple(x.view(n1, ld)[:, :n2].cpu() for x in (phi, psi)))
+    for g in got[1:]:
+        assert torch.equal(g[0], got[0][0]) and torch.equal(g[1], got[0][1])
+    phi_o, psi_o = oracle.corr2d(S1, S2)
+    assert rel_fro(got[0][0].numpy(), phi_o) <= TOL[prec]
+    assert rel_fro(got[0][1].numpy(), psi_o) <= TOL[prec]
+
+
 def test_hetero_circular_and_refs(gpu):
     m, n1, n2 = 18, 90, 70
     S1, S2 = _rand(m, n1, 40), _rand(m, n2, 41)
