@@ -374,32 +374,37 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
     phi = torch.empty(ocur, dtype=torch.float32, device=dev)
     psi = torch.empty(ocur, dtype=torch.float32, device=dev)
     spec = [(it.m, it.n, o, 0, oo) for it, o, oo in zip(items, offs, ooffs)]
-    res = {}
-    for name, flags in (("graph", 0), ("sequential", B.FLAG_SEQUENTIAL)):
-        plan = B.Plan(B.corr2d_desc_init(prec="f32", out_layout="upper_packed", flags=flags),
-                      items=spec)
-        ws = plan.workspace(dev)
-        call = lambda: B.corr2d_batched(plan.handle, y, phi, psi, ws)
-        res[name] = time_calls(torch, call, 5)
-        if name == "graph":
-            gp = phi.double().cpu().numpy()
-            gq = psi.double().cpu().numpy()
-        del plan, ws
-    errs_p, errs_q = [], []
+    # sampled entries of every 32nd data set, from the oracle
+    samples = []
     for k in range(0, len(items), 32):
         it, Sd, oo = items[k], data[k], ooffs[k]
         i, j = sample_pairs(it.n, 200, 100 + k, [])
         pe, qe = oracle.corr2d_entries(Sd, i, j)
         pidx = oo + i * it.n - (i * (i - 1)) // 2 + (j - i)
-        errs_p.append(rel_fro(gp[pidx], pe))
-        errs_q.append(rel_fro(gq[pidx], qe))
+        samples.append((torch.as_tensor(pidx, device=dev), pe, qe))
+    res, errs = {}, {}
+    for name, prec, flags in (("graph", "f32", 0), ("sequential", "f32", B.FLAG_SEQUENTIAL),
+                              ("split", "split_bf16", 0)):
+        plan = B.Plan(B.corr2d_desc_init(prec=prec, out_layout="upper_packed", flags=flags),
+                      items=spec)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_batched(plan.handle, y, phi, psi, ws)
+        res[name] = time_calls(torch, call, 5)
+        if name != "sequential":
+            errs[name] = (max(rel_fro(phi[ix].double().cpu().numpy(), pe) for ix, pe, _ in samples),
+                          max(rel_fro(psi[ix].double().cpu().numpy(), qe) for ix, _, qe in samples))
+        del plan, ws
     entries = sum(it.n * (it.n + 1) // 2 for it in items)
-    out.append({"workload": f"batch of {len(items)} homocorrelations, m in 8..200, n in 256..8192, "
-                            "FP32, upper triangles",
+    desc = f"batch of {len(items)} homocorrelations, m in 8..200, n in 256..8192, "
+    out.append({"workload": desc + "FP32, upper triangles",
                 "prec": "f32", "ms_per_call": res["graph"], "entries_per_s": entries / (res["graph"] * 1e-3),
                 "sequential_ms_per_call": res["sequential"],
                 "graph_speedup": res["sequential"] / res["graph"],
-                "err_phi": max(errs_p), "err_psi": max(errs_q)})
+                "err_phi": errs["graph"][0], "err_psi": errs["graph"][1]})
+    out.append({"workload": desc + "split-BF16, upper triangles",
+                "prec": "split_bf16", "ms_per_call": res["split"],
+                "entries_per_s": entries / (res["split"] * 1e-3),
+                "err_phi": errs["split"][0], "err_psi": errs["split"][1]})
     del phi, psi, y
     torch.cuda.empty_cache()
     return out
