@@ -304,6 +304,38 @@ def test_hetero_parity(gpu, prec, m, n1, n2):
     assert rel_fro(_np(psi), psi_o) <= TOL[prec]
 
 
+@pytest.mark.parametrize("m,n1,n2", [(256, 640, 0), (181, 500, 0), (128, 400, 300)])
+def test_split_error_within_elementwise_bound(gpu, m, n1, n2):
+    """Every split-BF16 entry lies within its own bound, whatever the
+    cancellation: the split products err by at most 2^-15 |a||b| (lo.lo
+    dropped, lo rounded), FP32 accumulation of 3K products by 3K 2^-24
+    sum|a||b|, the FP32 transform by ~1e-6 relative; with sum|a_k||b_k| <=
+    ||a|| ||b|| and ||a_i|| = sqrt(m) ||y_i|| (Parseval on the packed half
+    spectrum), |err_ij| <= 2^-13 ||y_i|| ||(N y)_j|| / (m - 1) for Psi and
+    the same with y_j for Phi (FFT transform at m = 256, table product at
+    m = 181, a heterocorrelation)."""
+    S1 = _rand(m, n1, 760 + m)
+    S2 = _rand(m, n2, 761 + m) * 3.0 if n2 else None
+    phi_o, psi_o = oracle.corr2d(S1, S2)
+    if n2:
+        phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), prec="split_bf16")
+    else:
+        phi, psi, _, _ = B.homo(_t(S1, gpu), prec="split_bf16")
+    phi, psi = _np(phi), _np(psi)
+    Y1, _ = oracle.dynamic(S1)
+    Y2 = Y1 if S2 is None else oracle.dynamic(S2)[0]
+    ny1 = np.linalg.norm(Y1, axis=0)
+    ny2 = np.linalg.norm(Y2, axis=0)
+    nz2 = np.linalg.norm(oracle.noda_transform(Y2), axis=0)
+    tau = 2.0 ** -13
+    bound_phi = tau * np.outer(ny1, ny2) / (m - 1)
+    bound_psi = tau * np.outer(ny1, nz2) / (m - 1)
+    assert np.all(np.abs(phi - phi_o) <= bound_phi)
+    assert np.all(np.abs(psi - psi_o) <= bound_psi)
+    # the bound is not vacuous: typical entries are far above it
+    assert np.median(np.abs(phi_o) / bound_phi) > 10.0
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
 def test_hetero_direct_and_staged_stores_agree(gpu, prec):
     """Interior tiles of a heterocorrelation are stored straight from the
