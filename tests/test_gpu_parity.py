@@ -311,12 +311,16 @@ def test_hetero_parity(gpu, prec, m, n1, n2):
 # 3K 2^-24 sum|a||b| (4.6e-5 at K = 256), the FP32 transform by ~1e-6;
 # FP32: operands rounded by 2^-24, K-term FP32 accumulation and the FP32
 # transform (each <= 1.5e-5 worst case at K = 256); BF16: operands rounded by
-# u, products by 2u + u^2, plus accumulation; FP64: the FP64 transform and
+# u, products by 2u + u^2, plus accumulation; FP16 (u = 2^-11) and FP8 e4m3
+# (u = 2^-4) the same, per-band scaling putting each column's largest values
+# near the top of the format's range, so that subnormal errors are
+# negligible against the column norms; FP64: the FP64 transform and
 # accumulation.
-ELEMENT_TAU = {"split_bf16": 2.0 ** -13, "f32": 2.0 ** -14, "bf16": 2.0 ** -6, "f64": 2.0 ** -40}
+ELEMENT_TAU = {"split_bf16": 2.0 ** -13, "f32": 2.0 ** -14, "bf16": 2.0 ** -6, "f64": 2.0 ** -40,
+               "f16": 2.0 ** -9, "fp8_e4m3": 2.0 ** -2}
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "f32", "bf16", "f64"])
+@pytest.mark.parametrize("prec", ["split_bf16", "f32", "bf16", "f64", "f16", "fp8_e4m3"])
 @pytest.mark.parametrize("m,n1,n2", [(256, 640, 0), (181, 500, 0), (128, 400, 300)])
 def test_error_within_elementwise_bound(gpu, prec, m, n1, n2):
     """Every entry lies within its own bound, whatever its cancellation:
@@ -345,7 +349,9 @@ def test_error_within_elementwise_bound(gpu, prec, m, n1, n2):
     assert np.all(np.abs(psi - psi_o) <= bound_psi)
     # the bound is not vacuous: typical entries lie above it (|cos| ~ 1/sqrt(m)
     # against tau)
-    assert np.median(np.abs(phi_o) / bound_phi) > (10.0 if tau <= 2.0 ** -13 else 1.5)
+    # (FP8's bound only catches gross errors)
+    if tau <= 2.0 ** -6:
+        assert np.median(np.abs(phi_o) / bound_phi) > (10.0 if tau <= 2.0 ** -9 else 1.5)
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
