@@ -13,6 +13,24 @@ TOL = {"f64": 1e-12, "f32": 1e-5, "split_bf16": 1e-5, "bf16": 2 * 2.0 ** -8,
        "f16": 2 * 2.0 ** -11, "fp8_e4m3": 2 * 2.0 ** -4}
 BF16_BAND_TOL = 2e-3
 
+# Per-element bound factors tau: |err_ij| <= tau ||y_i|| ||(N y)_j|| / (m-1)
+# for Psi (||y_j|| for Phi), in either basis (Fourier: c = 1/(m(m-1)) and
+# ||a_i|| = sqrt(m) ||y_i|| by Parseval; time: c = 1/(m-1), a = y, b = N y),
+# through sum|a_k||b_k| <= ||a|| ||b||.
+# split-BF16: with unit roundoff u = 2^-8 of BF16, |x - hi| <= u|x| and lo
+# carries u|lo| <= u^2|x|, so the products err by at most 3 u^2 |a||b|
+# (lo.lo dropped, lo rounded), FP32 accumulation of 3K products by
+# 3K 2^-24 sum|a||b| (4.6e-5 at K = 256), the FP32 transform by ~1e-6;
+# FP32: operands rounded by 2^-24, K-term FP32 accumulation and the FP32
+# transform (each <= 1.5e-5 worst case at K = 256); BF16: operands rounded by
+# u, products by 2u + u^2, plus accumulation; FP16 (u = 2^-11) and FP8 e4m3
+# (u = 2^-4) the same, per-band scaling putting each column's largest values
+# near the top of the format's range, so that subnormal errors are
+# negligible against the column norms; FP64: the FP64 transform and
+# accumulation.
+ELEMENT_TAU = {"split_bf16": 2.0 ** -13, "f32": 2.0 ** -14, "bf16": 2.0 ** -6, "f64": 2.0 ** -40,
+               "f16": 2.0 ** -9, "fp8_e4m3": 2.0 ** -2}
+
 
 def rel_fro(g, o):
     g = np.asarray(g, dtype=np.float64)

@@ -14,8 +14,8 @@ import oracle
 from paper_1808_00685_amd import binding as B
 from paper_1808_00685_amd import synth
 
-from .gpu_helpers import (TOL, check_homo_structure, packed_index, rel_fro, unpack_upper,
-                          unpack_upper_aligned)
+from .gpu_helpers import (ELEMENT_TAU, TOL, check_homo_structure, packed_index, rel_fro,
+                          unpack_upper, unpack_upper_aligned)
 
 pytestmark = pytest.mark.gpu
 
@@ -302,22 +302,6 @@ def test_hetero_parity(gpu, prec, m, n1, n2):
     phi, psi, _, _ = B.hetero(_t(S1, gpu), _t(S2, gpu), prec=prec)
     assert rel_fro(_np(phi), phi_o) <= TOL[prec]
     assert rel_fro(_np(psi), psi_o) <= TOL[prec]
-
-
-# Per-element bound factors tau (|err_ij| <= tau ||y_i|| ||(N y)_j|| / (m-1)):
-# split-BF16: with unit roundoff u = 2^-8 of BF16, |x - hi| <= u|x| and lo
-# carries u|lo| <= u^2|x|, so the products err by at most 3 u^2 |a||b|
-# (lo.lo dropped, lo rounded), FP32 accumulation of 3K products by
-# 3K 2^-24 sum|a||b| (4.6e-5 at K = 256), the FP32 transform by ~1e-6;
-# FP32: operands rounded by 2^-24, K-term FP32 accumulation and the FP32
-# transform (each <= 1.5e-5 worst case at K = 256); BF16: operands rounded by
-# u, products by 2u + u^2, plus accumulation; FP16 (u = 2^-11) and FP8 e4m3
-# (u = 2^-4) the same, per-band scaling putting each column's largest values
-# near the top of the format's range, so that subnormal errors are
-# negligible against the column norms; FP64: the FP64 transform and
-# accumulation.
-ELEMENT_TAU = {"split_bf16": 2.0 ** -13, "f32": 2.0 ** -14, "bf16": 2.0 ** -6, "f64": 2.0 ** -40,
-               "f16": 2.0 ** -9, "fp8_e4m3": 2.0 ** -2}
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "f32", "bf16", "f64", "f16", "fp8_e4m3"])

@@ -10,7 +10,7 @@ import oracle
 from paper_1808_00685_amd import binding as B
 from paper_1808_00685_amd import synth
 
-from .gpu_helpers import BF16_BAND_TOL, TOL, packed_index, rel_fro
+from .gpu_helpers import BF16_BAND_TOL, ELEMENT_TAU, TOL, packed_index, rel_fro
 from .lag_pairs import lag_sign_pairs
 
 pytestmark = pytest.mark.gpu
@@ -38,7 +38,10 @@ def large():
     S, meta = synth.workload_large()
     i, j = _sample_pairs(S.shape[1], 6000, 3, centers=np.round(meta["centers"]).astype(int))
     phi_o, psi_o = oracle.corr2d_entries(S, i, j)
-    return S, i, j, phi_o, psi_o
+    Y, _ = oracle.dynamic(S)
+    ny = np.linalg.norm(Y, axis=0)
+    nz = np.linalg.norm(oracle.noda_transform(Y), axis=0)
+    return S, i, j, phi_o, psi_o, ny, nz
 
 
 @pytest.mark.parametrize("prec,basis,tol,flags", [
@@ -53,7 +56,7 @@ def test_large_homo_sampled(gpu, large, prec, basis, tol, flags):
     through the radix FFT transform (the default at this m) and, forced by the
     flag, the table product."""
     import torch
-    S, i, j, phi_o, psi_o = large
+    S, i, j, phi_o, psi_o, ny, nz = large
     n = S.shape[1]
     phi, psi, plan, ws = B.homo(torch.as_tensor(S, device=gpu), prec=prec, basis=basis,
                                 layout="upper_packed", flags=flags)
@@ -64,6 +67,11 @@ def test_large_homo_sampled(gpu, large, prec, basis, tol, flags):
     e_phi, e_psi = rel_fro(g_phi, phi_o), rel_fro(g_psi, psi_o)
     print(f"large {prec}/{basis}/flags={flags}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
     assert e_phi <= tol and e_psi <= tol
+    # every sampled entry within its own bound (see gpu_helpers.ELEMENT_TAU)
+    m = S.shape[0]
+    tau = ELEMENT_TAU[prec]
+    assert np.all(np.abs(g_phi - phi_o) <= tau * ny[i] * ny[j] / (m - 1))
+    assert np.all(np.abs(g_psi - psi_o) <= tau * ny[i] * nz[j] / (m - 1))
     d = torch.as_tensor(packed_index(np.arange(n), np.arange(n), n), device=gpu)
     assert torch.all(psi[d] == 0)
     del phi, psi, ws
