@@ -127,14 +127,17 @@ def hetero_data():
     i = np.concatenate([rng.integers(0, S1.shape[1], 5000), np.repeat(c1, len(c2))])
     j = np.concatenate([rng.integers(0, S2.shape[1], 5000), np.tile(c2, len(c1))])
     phi_o, psi_o = oracle.corr2d_entries(S1, i, j, S2=S2)
-    return S1, S2, meta, i, j, phi_o, psi_o, len(c1) * len(c2)
+    Y1, Y2 = oracle.dynamic(S1)[0], oracle.dynamic(S2)[0]
+    norms = (np.linalg.norm(Y1, axis=0), np.linalg.norm(Y2, axis=0),
+             np.linalg.norm(oracle.noda_transform(Y2), axis=0))
+    return S1, S2, meta, i, j, phi_o, psi_o, len(c1) * len(c2), norms
 
 
 @pytest.mark.parametrize("prec", ["f16", "fp8_e4m3", "split_bf16"])
 def test_hetero_workload_sampled(gpu, hetero_data, prec):
     """m=128, 8192 x 2048 heterocorrelation with per-band scaling."""
     import torch
-    S1, S2, meta, i, j, phi_o, psi_o, ncoupled = hetero_data
+    S1, S2, meta, i, j, phi_o, psi_o, ncoupled, (ny1, ny2, nz2) = hetero_data
     phi, psi, plan, ws = B.hetero(torch.as_tensor(S1, device=gpu), torch.as_tensor(S2, device=gpu),
                                   prec=prec)
     if prec in ("f16", "fp8_e4m3"):
@@ -145,6 +148,10 @@ def test_hetero_workload_sampled(gpu, hetero_data, prec):
     e_phi, e_psi = rel_fro(g_phi, phi_o), rel_fro(g_psi, psi_o)
     print(f"hetero {prec}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
     assert e_phi <= TOL[prec] and e_psi <= TOL[prec]
+    # every sampled entry within its own bound (gpu_helpers.ELEMENT_TAU)
+    m, tau = S1.shape[0], ELEMENT_TAU[prec]
+    assert np.all(np.abs(g_phi - phi_o) <= tau * ny1[i] * ny2[j] / (m - 1))
+    assert np.all(np.abs(g_psi - psi_o) <= tau * ny1[i] * nz2[j] / (m - 1))
     # sign of Psi at band-centre pairs agrees with the oracle where it is not tiny
     sel = slice(len(i) - ncoupled, len(i))
     big = np.abs(psi_o[sel]) > 0.05 * np.abs(psi_o[sel]).max()
