@@ -404,6 +404,36 @@ def test_phase_lag_sign_on_gpu(gpu):
         assert np.sign(psi[60, 190]) == np.sign(math.sin(ph1 - ph2))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "bf16", "f16"])
+@pytest.mark.parametrize("m", [32, 128])
+def test_fig1_cases_on_gpu(gpu, prec, m):
+    """The special cases of Fig. 1 (Sec. 2) through the GPU path (table
+    product at m = 32, radix FFT at m = 128): variables with one response
+    (amplitudes 1, 2.5, -0.5) correlate purely synchronously, Psi vanishing
+    to within each entry's bound and Phi signed by Noda's rules 1 and 2; a
+    quarter-period lag at a Fourier bin correlates purely asynchronously,
+    Phi vanishing to within the bound and Psi > 0 for the leading one."""
+    tau = ELEMENT_TAU[prec]
+
+    def norms(S):
+        Y, _ = oracle.dynamic(S)
+        return np.linalg.norm(Y, axis=0), np.linalg.norm(oracle.noda_transform(Y), axis=0)
+
+    base = _rand(m, 1, 4 + m)
+    S = np.hstack([base, 2.5 * base, -0.5 * base])
+    phi, psi, _ = _homo(S, gpu, prec=prec)
+    ny, nz = norms(S)
+    assert np.all(np.abs(psi) <= tau * np.outer(ny, nz) / (m - 1))
+    assert phi[0, 1] > 0 and phi[0, 2] < 0 and phi[1, 2] < 0
+    p = 3
+    t = np.arange(m)[:, None]
+    S = np.cos(2 * math.pi * p * t / m + np.array([math.pi / 2, 0.0])[None, :])
+    phi, psi, _ = _homo(S, gpu, prec=prec)
+    ny, nz = norms(S)
+    assert abs(phi[0, 1]) <= tau * ny[0] * ny[1] / (m - 1)
+    assert psi[0, 1] > 0.1 and psi[1, 0] < -0.1
+
+
 def test_determinism(gpu):
     S = _rand(30, 500, 60)
     a = _homo(S, gpu, prec="split_bf16")
