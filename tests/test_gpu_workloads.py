@@ -218,6 +218,13 @@ def test_batched_graph_matches_sequential_and_oracle(gpu, prec):
         pidx = oo + packed_index(i, j, it.n)
         assert rel_fro(gp[pidx], po) <= TOL[prec], k
         assert rel_fro(gq[pidx], qo) <= TOL[prec], k
+        # and every sampled entry within its own bound (gpu_helpers.ELEMENT_TAU)
+        Y, _ = oracle.dynamic(S)
+        ny = np.linalg.norm(Y, axis=0)
+        nz = np.linalg.norm(oracle.noda_transform(Y), axis=0)
+        tau = ELEMENT_TAU[prec]
+        assert np.all(np.abs(gp[pidx] - po) <= tau * ny[i] * ny[j] / (it.m - 1)), k
+        assert np.all(np.abs(gq[pidx] - qo) <= tau * ny[i] * nz[j] / (it.m - 1)), k
 
 
 def test_batched_full_layout_and_no_graph(gpu):
