@@ -3,15 +3,21 @@
 
 One step = one corr2d_homo call through the C ABI on the m=256 x n=16384
 band workload (128 Lorentzian/Gaussian bands, amplitudes 1e-3..1e2, noise
-1e-4; upper triangle stored, FP32 output): FP64 centring, transform tables,
-FP32 MFMA transform to split-BF16 Fourier operands, split-BF16 MFMA
-contraction with FP64 epilogue.  Inputs are resident in HBM before timing.
+1e-4; upper triangle stored, FP32 output): the FFT tables, the radix FFT
+transform with the FP64 centring fused in (m = 256 is a power of two in
+[128, 1024]) writing split-BF16 Fourier operands, and the split-BF16 MFMA
+contraction with its FP64 epilogue.  Inputs are resident in HBM before
+timing.
 
 Prints ONE JSON line: throughput in correlation entries/s (stored
 (Phi, Psi) pairs), the roofline of the contraction kernel (timed alone with
 HIP events on the call's stream through the library's timing hook), the
 error against the FP64 oracle on sampled entries, the same measurements for
 the plain FP32, FP64 and BF16 forms, and the oracle timed on the host.
+
+The oracle serves two purposes here, both outside every timed region: the
+CPU baseline, and the reference values of the sampled entries behind each
+error figure.  Every timed call runs through the HIP library alone.
 """
 from __future__ import annotations
 
