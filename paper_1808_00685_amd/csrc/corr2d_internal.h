@@ -103,6 +103,12 @@ struct InterpJob {
 };
 
 // One correlation contraction (a homocorrelation or a heterocorrelation).
+// Outputs of a call up to this size (both planes) are written with
+// system-scope stores by the direct epilogue, larger ones non-temporally:
+// measured on the 16-bit kernel, system-scope stores are 3-10 % faster while
+// the outputs fit the 256 MB memory-side cache, and 10-23 % slower beyond.
+constexpr int64_t kNearStoreBytes = int64_t(192) << 20;
+
 struct CorrJob {
     const void* L0; const void* L1;   // left operand planes (set 1, A)
     const void* RA0; const void* RA1; // right synchronous operand (set 2, A)
@@ -119,6 +125,8 @@ struct CorrJob {
     int32_t group;      // column tiles per L2 group
     int32_t scaled;     // operands carry per-band power-of-two scales
     int32_t ratio;      // row tile height / column tile width (homo tile order)
+    int32_t store_near; // 1: the call's outputs fit the memory-side cache (see
+                        // kNearStoreBytes): direct stores at system scope
     int64_t ntiles;
     double c;           // FP64 normalization of the contraction
 };

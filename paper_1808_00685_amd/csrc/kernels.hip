@@ -1342,6 +1342,13 @@ __device__ inline void put4(OT* o, int64_t idx, V4<OT> v) {
     }
 }
 
+// A store at system scope (sc0 sc1), for calls whose outputs fit the
+// memory-side cache (kNearStoreBytes); a vector store, written in asm for
+// its cache-policy bits.
+__device__ inline void store_near(float* p, float v) {
+    asm volatile("global_store_dword %0, %1, off sc0 sc1" : : "v"(p), "v"(v) : "memory");
+}
+
 // One output element: the row exponent applied in the output type, and a
 // non-temporal store for FP32 (as in put4).
 __device__ inline float unscale1(float v, int e) { return ldexpf(v, e); }
@@ -1748,31 +1755,38 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
         // lines here, so no staging through LDS is needed.  The block's 32
         // rows lie in one 32-row band of the upper layout and share its row
         // length (the row stride for the full layout).  Non-temporal stores,
-        // as in put4.
+        // as in put4, or system-scope ones when the call's outputs fit the
+        // memory-side cache.
         float* out = (float*)(psi ? C.psi : C.phi);
+        auto direct = [&](auto near) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int64_t ia = i0 + wi * 64 + a * 32;
-            const int64_t base = hfull ? ia * C.ld_out : aligned_row_base(ia, C.n1);
-            const uint32_t len = hfull ? (uint32_t)C.ld_out
-                                       : (((uint32_t)C.n1 + 31u) & ~31u) - 32u * (uint32_t)(ia >> 5);
-            int4 re[4];   // row exponents of rows ia + 8k + 4g .. + 3
+            for (int a = 0; a < 2; ++a) {
+                const int64_t ia = i0 + wi * 64 + a * 32;
+                const int64_t base = hfull ? ia * C.ld_out : aligned_row_base(ia, C.n1);
+                const uint32_t len = hfull ? (uint32_t)C.ld_out
+                                           : (((uint32_t)C.n1 + 31u) & ~31u) - 32u * (uint32_t)(ia >> 5);
+                int4 re[4];   // row exponents of rows ia + 8k + 4g .. + 3
 #pragma unroll
-            for (int k = 0; k < 4; ++k) re[k] = *(const int4*)(sexp + wi * 64 + a * 32 + 8 * k + 4 * g);
+                for (int k = 0; k < 4; ++k) re[k] = *(const int4*)(sexp + wi * 64 + a * 32 + 8 * k + 4 * g);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int jl = wj * 64 + b * 32 + (lane & 31);
-                const double fc = ldexp(C.c, sexp[TM + (psi ? kTileN2 : 0) + jl]);
-                float* o = out + base + j0 + jl;
+                for (int b = 0; b < 2; ++b) {
+                    const int jl = wj * 64 + b * 32 + (lane & 31);
+                    const double fc = ldexp(C.c, sexp[TM + (psi ? kTileN2 : 0) + jl]);
+                    float* o = out + base + j0 + jl;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int k = r >> 2, q = r & 3;
-                    const int e = q == 0 ? re[k].x : q == 1 ? re[k].y : q == 2 ? re[k].z : re[k].w;
-                    __builtin_nontemporal_store(ldexpf((float)((double)acc[a][b][r] * fc), e),
-                                                o + mul64(8 * k + 4 * g + q, len));
+                    for (int r = 0; r < 16; ++r) {
+                        const int k = r >> 2, q = r & 3;
+                        const int e = q == 0 ? re[k].x : q == 1 ? re[k].y : q == 2 ? re[k].z : re[k].w;
+                        float* po = o + mul64(8 * k + 4 * g + q, len);
+                        const float v = ldexpf((float)((double)acc[a][b][r] * fc), e);
+                        if constexpr (decltype(near)::value) store_near(po, v);
+                        else __builtin_nontemporal_store(v, po);
+                    }
                 }
             }
-        }
+        };
+        if (C.store_near) direct(std::true_type{});
+        else direct(std::false_type{});
         return;
     }
 #pragma unroll
