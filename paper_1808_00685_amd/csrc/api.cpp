@@ -425,10 +425,12 @@ CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1
     C.scaled = p->scale;
     C.ntiles = homo ? triangle_tiles(C.tiles_i, C.ratio) : (int64_t)C.tiles_i * C.tiles_j;
     C.c = c;
-    // both output planes of this call (batched plans write far more)
-    const int64_t elems = (!homo || layout == L_FULL) ? g1.n * ld_out : g1.n * (g1.n + 32) / 2;
-    const int64_t out_bytes = 2 * elems * (C.out_f64 ? 8 : 4);
-    C.store_near = !p->batched && out_bytes <= kNearStoreBytes;
+    // both output planes of this call (batched plans write far more); in
+    // floating point, as a caller's row stride can be arbitrarily large
+    const double rows = (double)g1.n;
+    const double elems = (!homo || layout == L_FULL) ? rows * (double)ld_out : rows * (rows + 32.0) / 2.0;
+    const double out_bytes = 2.0 * elems * (C.out_f64 ? 8.0 : 4.0);
+    C.store_near = !p->batched && out_bytes <= (double)kNearStoreBytes;
     return C;
 }
 
