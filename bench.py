@@ -12,12 +12,14 @@ timing.
 Prints ONE JSON line: throughput in correlation entries/s (stored
 (Phi, Psi) pairs), the roofline of the contraction kernel (timed alone with
 HIP events on the call's stream through the library's timing hook), the
-error against the FP64 oracle on sampled entries, the same measurements for
-the plain FP32, FP64 and BF16 forms, and the oracle timed on the host.
+error against the FP64 oracle over the full matrices, the same measurements
+for the plain FP32, FP64 and BF16 forms and the other workloads, and the
+oracle timed on the host.
 
 The oracle serves two purposes here, both outside every timed region: the
-CPU baseline, and the reference values of the sampled entries behind each
-error figure.  Every timed call runs through the HIP library alone.
+CPU baseline (with the oracle's time on every workload), and the reference
+values behind each error figure (every entry of every output, computed in
+row blocks).  Every timed call runs through the HIP library alone.
 """
 from __future__ import annotations
 
@@ -40,19 +42,70 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "split_bf16": 2500.0, "bf16": 2500.0,
 HBM_GBPS = 8000.0
 
 
-def sample_pairs(n, count, seed, centers):
-    rng = np.random.default_rng(seed)
-    i = rng.integers(0, n, count)
-    j = rng.integers(0, n, count)
-    c = np.unique(np.clip(np.round(centers).astype(np.int64), 0, n - 1))
-    ci, cj = np.meshgrid(c, c, indexing="ij")
-    i = np.concatenate([i, ci.ravel()])
-    j = np.concatenate([j, cj.ravel()])
-    return np.minimum(i, j).astype(np.int64), np.maximum(i, j).astype(np.int64)
-
-
 def rel_fro(g, o):
     return float(np.linalg.norm(g - o) / np.linalg.norm(o))
+
+
+def upper_oracle(oracle, torch, S, dev, block=1024):
+    """The oracle's homocorrelation (Noda's kernel and norm) over the upper
+    triangle, computed in row blocks of the direct route, as packed FP64
+    planes on `dev`; returns (phi, psi, seconds the oracle took)."""
+    t0 = time.perf_counter()
+    Y, _ = oracle.dynamic(S)
+    secs = time.perf_counter() - t0
+    m, n = Y.shape
+    tot = n * (n + 1) // 2
+    phi = torch.empty(tot, dtype=torch.float64, device=dev)
+    psi = torch.empty(tot, dtype=torch.float64, device=dev)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        t0 = time.perf_counter()
+        po, qo = oracle.corr_ht_block(Y, Y, r0, r1, r0, n)
+        secs += time.perf_counter() - t0
+        mask = np.triu(np.ones((r1 - r0, n - r0), dtype=bool))
+        a, b = r0 * n - (r0 * (r0 - 1)) // 2, r1 * n - (r1 * (r1 - 1)) // 2
+        phi[a:b] = torch.as_tensor(po[mask], device=dev)
+        psi[a:b] = torch.as_tensor(qo[mask], device=dev)
+        del po, qo, mask
+    return phi, psi, secs
+
+
+def packed_diag(torch, n, dev):
+    i = torch.arange(n, device=dev, dtype=torch.int64)
+    return i * n - (i * (i - 1)) // 2
+
+
+def aligned_to_packed_index(torch, n, dev):
+    """Positions, in an UPPER_ALIGNED plane, of the entries of the packed
+    order: (i, j) at i N32 - 32 (16 q (q-1) + r q) + (j - 32 q), i = 32 q + r."""
+    i = torch.arange(n, device=dev, dtype=torch.int64)
+    lens = n - i
+    rows = torch.repeat_interleave(i, lens)
+    j = torch.arange(rows.numel(), device=dev, dtype=torch.int64) - (torch.cumsum(lens, 0) - lens)[rows] + rows
+    n32 = (n + 31) // 32 * 32
+    q, r = rows // 32, rows % 32
+    return rows * n32 - 32 * (16 * q * (q - 1) + r * q) + (j - 32 * q)
+
+
+def full_counts(torch, g, o, diag, chunk=1 << 25):
+    """(sum of squared errors, sum of squared oracle values) over the full
+    matrix of a homocorrelation given as packed upper-triangle planes (each
+    entry off the diagonal stands for two), in FP64 on the planes' device."""
+    num = den = 0.0
+    for a in range(0, o.numel(), chunk):
+        b = min(o.numel(), a + chunk)
+        d = g[a:b].double() - o[a:b]
+        num += float((d * d).sum())
+        den += float((o[a:b] * o[a:b]).sum())
+    dd = g[diag].double() - o[diag]
+    num = 2.0 * num - float((dd * dd).sum())
+    den = 2.0 * den - float((o[diag] * o[diag]).sum())
+    return num, den
+
+
+def full_rel_err(torch, g, o, diag):
+    num, den = full_counts(torch, g, o, diag)
+    return math.sqrt(num / den) if den > 0 else math.sqrt(num)
 
 
 # Table 1 of the paper (Sec. 4.3): mean time of one corr2d() homocorrelation
@@ -127,9 +180,12 @@ LAYOUT_TEXT = {"upper_aligned": "rows aligned to 128 bytes",
                "upper_packed": "packed rows"}
 
 
-def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracle_vals,
+def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, ref,
                 layout="upper_packed", alpha=0.0):
-    """Time `steps` calls; returns a dict of measurements for this form."""
+    """Time `steps` calls; returns a dict of measurements for this form, with
+    its error against the oracle over the full matrices.  ref = (oracle Phi,
+    oracle Psi, diagonal positions, aligned-layout gather index), the oracle's
+    values packed as upper triangles on the GPU."""
     out_dtype = "f64" if prec == "f64" else "f32"
     plan = B.Plan(m=m, n1=n, n2=0, prec=prec, basis=basis, out_layout=layout,
                   in_dtype="f64", out_dtype=out_dtype, scale_alpha=alpha)
@@ -145,20 +201,20 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        B.corr2d_plan_set_timing_events(plan.handle, evs[2 * s], evs[2 * s + 1])
+        B.corr2d_set_timing_events(evs[2 * s], evs[2 * s + 1])
         B.corr2d_homo(plan.handle, y, None, phi, psi, ws, stream=stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    B.corr2d_plan_set_timing_events(plan.handle, None, None)
+    B.corr2d_set_timing_events(None, None)
     kms = [ev.elapsed_ms(evs[2 * s], evs[2 * s + 1]) for s in range(steps)]
     ev.destroy(evs)
-    i, j = sample
+    o_phi, o_psi, diag, a2p = ref
     if layout == "upper_packed":
-        idx = torch.as_tensor(i * n - (i * (i - 1)) // 2 + (j - i), device=y.device)
+        err_phi = full_rel_err(torch, phi, o_phi, diag)
+        err_psi = full_rel_err(torch, psi, o_psi, diag)
     else:
-        idx = torch.as_tensor(B.upper_aligned_index(i, j, n), device=y.device)
-    g_phi = phi[idx].double().cpu().numpy()
-    g_psi = psi[idx].double().cpu().numpy()
+        err_phi = full_rel_err(torch, phi[a2p], o_phi, diag)
+        err_psi = full_rel_err(torch, psi[a2p], o_psi, diag)
     info = plan.info
     entries = n * (n + 1) // 2
     alg_flops = 4.0 * m * entries
@@ -180,8 +236,8 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, sample, oracl
         "mfma_peak_tflops": PEAK_TFLOPS[prec],
         "mfma_executed_frac": executed / (kernel_ms * 1e-3) / 1e12 / PEAK_TFLOPS[prec],
         "kernel_hbm_GBps": kernel_bytes / (kernel_ms * 1e-3) / 1e9,
-        "err_phi": rel_fro(g_phi, oracle_vals[0]),
-        "err_psi": rel_fro(g_psi, oracle_vals[1]),
+        "err_phi": err_phi,
+        "err_psi": err_psi,
         "tile": f"{info.tile_m}x{info.tile_n}",
         "alg_flops": alg_flops, "executed_flops": executed, "kernel_bytes": kernel_bytes,
     }
@@ -250,6 +306,24 @@ def cpu_baseline(oracle, S, target_s):
                       f"{calls * rows * n} (Phi, Psi) entries in {dt:.1f} s"}
 
 
+def host_cpu():
+    """The host's CPU model, logical CPUs and the CPUs this process may use."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def time_calls(torch, fn, reps, batches=3):
     """Wall time per call of `reps` back-to-back calls (ms), the fastest of
     `batches` batches: one host-side hiccup of a few ms would otherwise
@@ -275,21 +349,37 @@ def kernel_ms(B, torch, plan, call, ev, reps=7):
     it in whole."""
     evs = ev.create(2 * reps)
     for r in range(reps):
-        B.corr2d_plan_set_timing_events(plan.handle, evs[2 * r], evs[2 * r + 1])
+        B.corr2d_set_timing_events(evs[2 * r], evs[2 * r + 1])
         call()
     torch.cuda.synchronize()
     ms = [ev.elapsed_ms(evs[2 * r], evs[2 * r + 1]) for r in range(reps)]
-    B.corr2d_plan_set_timing_events(plan.handle, None, None)
+    B.corr2d_set_timing_events(None, None)
     ev.destroy(evs)
     return float(np.median(ms))
+
+
+def timed_oracle(oracle, fn, threads=None):
+    """Run fn() on the oracle (with `threads` OpenMP threads if given) and
+    return (result, seconds)."""
+    all_threads = oracle.threads()
+    if threads is not None:
+        oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        r = fn()
+        return r, time.perf_counter() - t0
+    finally:
+        oracle.set_threads(all_threads)
 
 
 def other_workloads(B, torch, oracle, synth, ev, dev):
     """The other workload configurations: small FP64 (latency), medium full
     FP32/FP64 (output-bound), heterocorrelation FP16/FP8 (output-bound) and
     the batch of 256 data sets (persistent graph against sequential
-    launches), each with its error against the oracle."""
-    out = []
+    launches), each with its error against the oracle over the full
+    matrices.  Also returns the oracle's own times on these workloads."""
+    out, otimes = [], []
+    nthreads = oracle.threads()
 
     # small: m = 11, n = 512, FP64, full output
     S, _ = synth.workload_small()
@@ -301,19 +391,29 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
     ws = plan.workspace(dev)
     call = lambda: B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
     ms = time_calls(torch, call, 50)
-    po, qo = oracle.corr2d(S)
+    (po, qo), t_all = timed_oracle(oracle, lambda: oracle.corr2d(S))
+    _, t_one = timed_oracle(oracle, lambda: oracle.corr2d(S), threads=1)
+    for th, t in ((nthreads, t_all), (1, t_one)):
+        otimes.append({"workload": f"m={m} n={n}, full", "threads": th, "seconds": t,
+                       "entries_per_s": n * n / t})
     out.append({"workload": f"homocorrelation m={m} n={n}, FP64, full output", "prec": "f64",
                 "ms_per_call": ms, "entries_per_s": n * n / (ms * 1e-3),
                 "err_phi": rel_fro(phi.cpu().numpy().reshape(n, n), po),
-                "err_psi": rel_fro(psi.cpu().numpy().reshape(n, n), qo)})
+                "err_psi": rel_fro(psi.cpu().numpy().reshape(n, n), qo),
+                "error_measure": "relative Frobenius, full matrices"})
     del plan, phi, psi, ws
 
     # medium: m = 64, n = 4096, FP32 and FP64, full output (mirror stored)
     S, meta = synth.workload_medium()
     m, n = S.shape
     y = torch.as_tensor(S, device=dev)
-    si, sj = sample_pairs(n, 2000, 7, meta["centers"][:16])
-    po, qo = oracle.corr2d_entries(S, si, sj)
+    (po, qo), t_all = timed_oracle(oracle, lambda: oracle.corr2d(S))
+    _, t_one = timed_oracle(oracle, lambda: oracle.corr2d(S), threads=1)
+    for th, t in ((nthreads, t_all), (1, t_one)):
+        otimes.append({"workload": f"m={m} n={n}, full", "threads": th, "seconds": t,
+                       "entries_per_s": n * n / t})
+    po_t, qo_t = torch.as_tensor(po, device=dev), torch.as_tensor(qo, device=dev)
+    del po, qo
     for prec in ("f32", "f64"):
         tdt = torch.float64 if prec == "f64" else torch.float32
         plan = B.Plan(m=m, n1=n, n2=0, prec=prec, in_dtype="f64", out_dtype=prec)
@@ -323,7 +423,6 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
         call = lambda: B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
         ms = time_calls(torch, call, 20)
         kms = kernel_ms(B, torch, plan, call, ev)
-        idx = torch.as_tensor(si * n + sj, device=dev)
         nbytes = 2 * n * n * (8 if prec == "f64" else 4)
         out.append({"workload": f"homocorrelation m={m} n={n}, full output", "prec": prec,
                     "ms_per_call": ms, "entries_per_s": n * n / (ms * 1e-3), "kernel_ms": kms,
@@ -331,9 +430,11 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
                                  "peak": HBM_GBPS, "unit": "GB/s",
                                  "frac": nbytes / (kms * 1e-3) / 1e9 / HBM_GBPS,
                                  "bytes_per_launch": nbytes},
-                    "err_phi": rel_fro(phi[idx].double().cpu().numpy(), po),
-                    "err_psi": rel_fro(psi[idx].double().cpu().numpy(), qo)})
+                    "err_phi": float(torch.linalg.norm(phi.double() - po_t.ravel()) / torch.linalg.norm(po_t)),
+                    "err_psi": float(torch.linalg.norm(psi.double() - qo_t.ravel()) / torch.linalg.norm(qo_t)),
+                    "error_measure": "relative Frobenius, full matrices"})
         del plan, phi, psi, ws
+    del po_t, qo_t
 
     # heterocorrelation: m = 128, n1 = 8192, n2 = 2048, FP16 and FP8, full output
     S1, S2, meta = synth.workload_hetero()
@@ -341,10 +442,12 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
     n2 = S2.shape[1]
     y1 = torch.as_tensor(S1, device=dev)
     y2 = torch.as_tensor(S2, device=dev)
-    rng = np.random.default_rng(9)
-    hi, hj = rng.integers(0, n1, 3000), rng.integers(0, n2, 3000)
-    po, qo = oracle.corr2d_entries(S1, hi, hj, S2=S2)
-    for prec in ("f16", "fp8_e4m3"):
+    (po, qo), t_all = timed_oracle(oracle, lambda: oracle.corr2d(S1, S2=S2))
+    otimes.append({"workload": f"hetero m={m} n1={n1} n2={n2}, full", "threads": nthreads,
+                   "seconds": t_all, "entries_per_s": n1 * n2 / t_all})
+    po_t, qo_t = torch.as_tensor(po, device=dev).ravel(), torch.as_tensor(qo, device=dev).ravel()
+    del po, qo
+    for prec in ("f16", "fp8_e4m3", "split_bf16"):
         plan = B.Plan(m=m, n1=n1, n2=n2, prec=prec, in_dtype="f64", out_dtype="f32")
         phi = torch.empty(n1 * n2, dtype=torch.float32, device=dev)
         psi = torch.empty(n1 * n2, dtype=torch.float32, device=dev)
@@ -352,7 +455,6 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
         call = lambda: B.corr2d_hetero(plan.handle, y1, None, y2, None, phi, psi, ws)
         ms = time_calls(torch, call, 20)
         kms = kernel_ms(B, torch, plan, call, ev)
-        idx = torch.as_tensor(hi * n2 + hj, device=dev)
         nbytes = 2 * n1 * n2 * 4
         out.append({"workload": f"heterocorrelation m={m} n1={n1} n2={n2}, full output",
                     "prec": prec, "ms_per_call": ms, "entries_per_s": n1 * n2 / (ms * 1e-3),
@@ -361,11 +463,23 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
                                  "peak": HBM_GBPS, "unit": "GB/s",
                                  "frac": nbytes / (kms * 1e-3) / 1e9 / HBM_GBPS,
                                  "bytes_per_launch": nbytes},
-                    "err_phi": rel_fro(phi[idx].double().cpu().numpy(), po),
-                    "err_psi": rel_fro(psi[idx].double().cpu().numpy(), qo)})
+                    "err_phi": float(torch.linalg.norm(phi.double() - po_t) / torch.linalg.norm(po_t)),
+                    "err_psi": float(torch.linalg.norm(psi.double() - qo_t) / torch.linalg.norm(qo_t)),
+                    "error_measure": "relative Frobenius, full matrices"})
         del plan, phi, psi, ws
+    del po_t, qo_t
 
-    # batch of 256 data sets, FP32, upper triangles
+    # batch of 256 data sets, FP32 and split-BF16, upper triangles
+    out.extend(batch_workload(B, torch, oracle, synth, dev, otimes))
+    torch.cuda.empty_cache()
+    return out, otimes
+
+
+def batch_workload(B, torch, oracle, synth, dev, otimes):
+    """The batch of 256 data sets: one graph replay of the persistent launch
+    (FP32 and split-BF16) and the FP32 sequential launches, timed; then every
+    data set's full Phi and Psi against the oracle (per-set relative
+    Frobenius errors; the worst set and the whole batch are reported)."""
     items = synth.batch_spec()
     data = [synth.batch_item_data(it) for it in items]
     offs, ooffs, cur, ocur = [], [], 0, 0
@@ -377,43 +491,60 @@ def other_workloads(B, torch, oracle, synth, ev, dev):
     y = torch.empty(cur, dtype=torch.float64, device=dev)
     for it, Sd, o in zip(items, data, offs):
         y[o:o + it.m * it.n] = torch.as_tensor(Sd.ravel(), device=dev)
-    phi = torch.empty(ocur, dtype=torch.float32, device=dev)
-    psi = torch.empty(ocur, dtype=torch.float32, device=dev)
     spec = [(it.m, it.n, o, 0, oo) for it, o, oo in zip(items, offs, ooffs)]
-    # sampled entries of every 32nd data set, from the oracle
-    samples = []
-    for k in range(0, len(items), 32):
-        it, Sd, oo = items[k], data[k], ooffs[k]
-        i, j = sample_pairs(it.n, 200, 100 + k, [])
-        pe, qe = oracle.corr2d_entries(Sd, i, j)
-        pidx = oo + i * it.n - (i * (i - 1)) // 2 + (j - i)
-        samples.append((torch.as_tensor(pidx, device=dev), pe, qe))
-    res, errs = {}, {}
+    res, outs = {}, {}
     for name, prec, flags in (("graph", "f32", 0), ("sequential", "f32", B.FLAG_SEQUENTIAL),
                               ("split", "split_bf16", 0)):
+        if name != "sequential":
+            outs[name] = (torch.empty(ocur, dtype=torch.float32, device=dev),
+                          torch.empty(ocur, dtype=torch.float32, device=dev))
+        phi, psi = outs["graph" if name == "sequential" else name]
         plan = B.Plan(B.corr2d_desc_init(prec=prec, out_layout="upper_packed", flags=flags),
                       items=spec)
         ws = plan.workspace(dev)
         call = lambda: B.corr2d_batched(plan.handle, y, phi, psi, ws)
         res[name] = time_calls(torch, call, 5)
-        if name != "sequential":
-            errs[name] = (max(rel_fro(phi[ix].double().cpu().numpy(), pe) for ix, pe, _ in samples),
-                          max(rel_fro(psi[ix].double().cpu().numpy(), qe) for ix, _, qe in samples))
         del plan, ws
+    del y
+    # every set's upper triangle against the oracle's
+    agg = {k: [0.0, 0.0, 0.0, 0.0] for k in outs}
+    worst = {k: (0.0, -1, 0.0, 0.0) for k in outs}
+    osecs = 0.0
+    for k, (it, Sd, oo) in enumerate(zip(items, data, ooffs)):
+        o_phi, o_psi, secs = upper_oracle(oracle, torch, Sd, dev)
+        osecs += secs
+        diag = packed_diag(torch, it.n, dev)
+        tot = it.n * (it.n + 1) // 2
+        for name, (phi, psi) in outs.items():
+            c_phi = full_counts(torch, phi[oo:oo + tot], o_phi, diag)
+            c_psi = full_counts(torch, psi[oo:oo + tot], o_psi, diag)
+            a = agg[name]
+            a[0] += c_phi[0]; a[1] += c_phi[1]; a[2] += c_psi[0]; a[3] += c_psi[1]
+            e_phi = math.sqrt(c_phi[0] / c_phi[1]) if c_phi[1] > 0 else math.sqrt(c_phi[0])
+            e_psi = math.sqrt(c_psi[0] / c_psi[1]) if c_psi[1] > 0 else math.sqrt(c_psi[0])
+            if max(e_phi, e_psi) > max(worst[name][2], worst[name][3]):
+                worst[name] = (0.0, k, e_phi, e_psi)
+        del o_phi, o_psi
     entries = sum(it.n * (it.n + 1) // 2 for it in items)
+    otimes.append({"workload": f"batch of {len(items)} sets, upper triangles", "threads": oracle.threads(),
+                   "seconds": osecs, "entries_per_s": entries / osecs})
     desc = f"batch of {len(items)} homocorrelations, m in 8..200, n in 256..8192, "
-    out.append({"workload": desc + "FP32, upper triangles",
-                "prec": "f32", "ms_per_call": res["graph"], "entries_per_s": entries / (res["graph"] * 1e-3),
-                "sequential_ms_per_call": res["sequential"],
-                "graph_speedup": res["sequential"] / res["graph"],
-                "err_phi": errs["graph"][0], "err_psi": errs["graph"][1]})
-    out.append({"workload": desc + "split-BF16, upper triangles",
-                "prec": "split_bf16", "ms_per_call": res["split"],
-                "entries_per_s": entries / (res["split"] * 1e-3),
-                "err_phi": errs["split"][0], "err_psi": errs["split"][1]})
-    del phi, psi, y
-    torch.cuda.empty_cache()
-    return out
+    rows = []
+    for name, prec, text in (("graph", "f32", "FP32"), ("split", "split_bf16", "split-BF16")):
+        a, w = agg[name], worst[name]
+        r = {"workload": desc + text + ", upper triangles", "prec": prec,
+             "ms_per_call": res[name], "entries_per_s": entries / (res[name] * 1e-3),
+             "err_phi": math.sqrt(a[0] / a[1]), "err_psi": math.sqrt(a[2] / a[3]),
+             "worst_set": {"index": w[1], "m": items[w[1]].m, "n": items[w[1]].n,
+                           "err_phi": w[2], "err_psi": w[3]},
+             "error_measure": "relative Frobenius over all data sets' full matrices; "
+                              "worst_set: the largest per-set error"}
+        if name == "graph":
+            r["sequential_ms_per_call"] = res["sequential"]
+            r["graph_speedup"] = res["sequential"] / res["graph"]
+        rows.append(r)
+    del outs
+    return rows
 
 
 def main():
@@ -456,37 +587,56 @@ def main():
         return
     m, n = args.m, args.n
     S, meta = synth.workload_large(m=m, n=n)
-    sample = sample_pairs(n, 3000, 5, meta["centers"][:48])
-    oracle_vals = oracle.corr2d_entries(S, sample[0], sample[1])
     y = torch.as_tensor(S, device=dev)
     ev = HipEvents()
+    # the oracle over the whole upper triangle (outside every timed region)
+    o_phi, o_psi, c3_secs = upper_oracle(oracle, torch, S, dev)
+    diag = packed_diag(torch, n, dev)
+    a2p = aligned_to_packed_index(torch, n, dev)
+    ref = (o_phi, o_psi, diag, a2p)
 
     layout = args.layout
     main_res = run_variant(B, torch, y, n, m, "split_bf16", "fourier", args.steps, args.warmup,
-                           ev, sample, oracle_vals, layout=layout)
+                           ev, ref, layout=layout)
     variants = []
     if not args.no_variants:
         vs = args.variant_steps
         # the headline form in the other upper-triangle layout
         other = "upper_packed" if layout == "upper_aligned" else "upper_aligned"
-        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, sample,
-                                    oracle_vals, layout=other))
+        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, ref,
+                                    layout=other))
         for prec, basis in (("f32", "fourier"), ("bf16", "fourier"), ("bf16", "time"),
                             ("f64", "fourier")):
-            variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, sample,
-                                        oracle_vals, layout=layout))
-        # Pareto scaling (alpha = 0.5) of the headline form
-        pareto_vals = oracle.corr2d_entries(S, sample[0], sample[1], alpha=0.5)
-        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, sample,
-                                    pareto_vals, alpha=0.5, layout=layout))
+            variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, ref,
+                                        layout=layout))
+        # Pareto scaling (alpha = 0.5) of the headline form: the oracle's
+        # values times its scaling factors (oracle.corr2d's alpha)
+        f = torch.as_tensor(oracle.scaling_factors(oracle.band_sd(oracle.dynamic(S)[0]), 0.5),
+                            device=dev)
+        ii = torch.arange(n, device=dev, dtype=torch.int64)
+        rows = torch.repeat_interleave(ii, n - ii)
+        cols = torch.arange(rows.numel(), device=dev, dtype=torch.int64) - diag[rows] + rows
+        w = f[rows] * f[cols]
+        del rows, cols
+        pref = (o_phi * w, o_psi * w, diag, a2p)
+        del w
+        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, pref,
+                                    alpha=0.5, layout=layout))
+        del pref
+    del ref, o_phi, o_psi, a2p
+    torch.cuda.empty_cache()
 
-    workloads = []
+    workloads, otimes = [], []
     if not args.no_workloads:
-        workloads = other_workloads(B, torch, oracle, synth, ev, dev)
+        workloads, otimes = other_workloads(B, torch, oracle, synth, ev, dev)
+    otimes.insert(0, {"workload": f"m={m} n={n}, upper triangle", "threads": oracle.threads(),
+                      "seconds": c3_secs, "entries_per_s": n * (n + 1) // 2 / c3_secs})
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(oracle, S, args.cpu_seconds)
+        cpu["host"] = host_cpu()
+        cpu["per_workload"] = otimes
 
     prof = profile_record() if (m, n, layout) == (256, 16384, "upper_aligned") else None
     alg = main_res["alg_flops"]
@@ -530,7 +680,8 @@ def main():
             "executed_frac": main_res["kernel_executed_tflops"] / PEAK_TFLOPS["split_bf16"],
         },
         "error_vs_oracle": {"phi": main_res["err_phi"], "psi": main_res["err_psi"],
-                            "sampled_entries": int(len(sample[0]))},
+                            "measure": "relative Frobenius over the full n x n matrices "
+                                       f"({n * (n + 1) // 2} stored entries compared)"},
         "cpu_baseline": cpu,
         "paper_context": paper_context(),
         "variants": [{k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in r.items()

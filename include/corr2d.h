@@ -228,15 +228,26 @@ typedef struct corr2d_plan_info {
 void corr2d_desc_init(corr2d_desc* d);
 
 /* Validate d and build a plan in host memory.  No device call is made.
+ * The descriptor carries the arguments of the paper's corr2d() call (Sec. 3,
+ * Sec. 4.2): the data sets' sizes, the reference (Ref1/Ref2 at call time),
+ * Norm (norm_mode), scaling (scale_alpha), Time/Int/N (interpolation,
+ * Sec. 4.1), plus this library's choices of arithmetic and output layout.
+ * A plan is immutable once made: the compute calls read it and never change
+ * it (a batched plan's cached graph and job buffer are internal, guarded by
+ * a lock).                                                                  
  * EINVAL: m < 2, n1 < 1, n2 < 0, a stride smaller than its row, an unknown
  * enum value, CUSTOM norm with a non-finite norm_value, UPPER_PACKED or
  * UPPER_ALIGNED for a heterocorrelation.  EUNSUPPORTED: FP8 with per-band scaling forced off.   */
 corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d);
 
-/* Batched homocorrelation of count independent data sets (count >= 1); the
- * common descriptor supplies precision, basis, kernel, norm, layout, dtypes
- * and flags (its m, n1, n2, strides are ignored).  Each set's outputs have
- * the common layout with row stride n.  Errors as corr2d_plan, per item.    */
+/* Batched homocorrelation of count independent data sets (count >= 1):
+ * corr2d(Mat1) of Sec. 3 applied to each set.  The paper measures that the
+ * per-call setup dominates small problems (Sec. 4.3, Table 1); a batched
+ * plan runs all sets through one chain of launches instead.  The common
+ * descriptor supplies precision, basis, kernel, norm, layout, dtypes and
+ * flags (its m, n1, n2, strides are ignored).  Each set's outputs have the
+ * common layout with row stride n.  Errors as corr2d_plan, per item;
+ * EUNSUPPORTED for interpolation.                                           */
 corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
                                   const corr2d_item* items, int64_t count);
 
@@ -244,14 +255,18 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
 corr2d_status corr2d_plan_destroy(corr2d_plan_t plan);
 
 /* Device workspace a call needs, in bytes (the caller allocates it; 256-byte
- * alignment required).  It holds the transform tables, the reference and
- * centred spectra, the packed contraction operands and scale vectors.        */
+ * alignment required).  It holds the intermediate results of the steps of
+ * Sec. 4.2: the reference spectrum (Eq. (ref)), the transform tables and
+ * the Fourier-transformed dynamic spectra (Eqs. (disFT), (symmeFT)) as the
+ * packed contraction operands, with their scale vectors.  EINVAL for a NULL
+ * argument.                                                                  */
 corr2d_status corr2d_workspace_bytes(corr2d_plan_t plan, size_t* bytes);
 
 corr2d_status corr2d_plan_get_info(corr2d_plan_t plan, corr2d_plan_info* info);
 
-/* Homocorrelation, the paper's corr2d(Mat1) (Sec. 3, Sec. 4.2) without
- * interpolation or scaling.
+/* Homocorrelation, the paper's corr2d(Mat1) (Sec. 3, Sec. 4.2), with the
+ * interpolation of Sec. 4.1 and the result scaling of Sec. 2 Eqs.
+ * (scalesyn), (scaleasyn) when the plan asks for them.
  *   y    device, m x ld_in1 of in_dtype
  *   ref  device, n1 doubles, or NULL for the perturbation mean spectrum
  *   phi, psi  device outputs of out_dtype in out_layout (n1 x n1)
@@ -268,19 +283,25 @@ corr2d_status corr2d_hetero(corr2d_plan_t plan, const void* y1, const double* re
                             const void* y2, const double* ref2, void* phi, void* psi,
                             void* ws, size_t ws_bytes, void* stream);
 
-/* Batched homocorrelation.  With neither SEQUENTIAL nor NO_GRAPH the whole
- * batch (prep and one persistent contraction launch) is replayed from a
- * hipGraph the plan captures on first use for these pointers and stream.    */
+/* Batched homocorrelation: corr2d(Mat1) (Sec. 3) of every data set of the
+ * plan.  y_base, phi_base, psi_base: device; each set at its item offsets.
+ * With neither SEQUENTIAL nor NO_GRAPH the whole batch (prep and one
+ * persistent contraction launch per tile shape) is replayed from a hipGraph
+ * the plan captures on first use for these pointers and stream; the job
+ * arrays are uploaded from a pinned host buffer that the plan allocates on
+ * its first call.  A call with other pointers or another stream than the
+ * previous one waits (on the host) for that previous call's job upload
+ * before it rewrites the buffer.                                           */
 corr2d_status corr2d_batched(corr2d_plan_t plan, const void* y_base, void* phi_base,
                              void* psi_base, void* ws, size_t ws_bytes, void* stream);
 
-/* Measurement hook: when set (hipEvent_t handles passed as void*, either may
- * be NULL), corr2d_homo and corr2d_hetero record `before` on the call's stream
+/* Measurement hook of the calling thread: when set (hipEvent_t handles
+ * passed as void*, either may be NULL), the calling thread's later
+ * corr2d_homo and corr2d_hetero calls record `before` on the call's stream
  * immediately before the contraction kernel and `after` immediately after
- * it, so a caller can time that kernel alone.  The plan keeps the handles
- * (it does not own them); pass NULLs to stop.  Not thread safe with calls in
- * flight on other threads.                                                    */
-corr2d_status corr2d_plan_set_timing_events(corr2d_plan_t plan, void* before, void* after);
+ * it, so that kernel can be timed alone.  The library keeps the handles
+ * (it does not own them) in thread-local storage; pass NULLs to stop.       */
+corr2d_status corr2d_set_timing_events(void* before, void* after);
 
 const char* corr2d_status_str(corr2d_status s);
 

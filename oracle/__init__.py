@@ -80,6 +80,7 @@ def lib():
         L.oracle_corr_ft_circular_entries.argtypes = [cl, cl, cl, dp, dp, ctypes.c_double,
                                                       cl, lp, lp, dp, dp]
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -99,6 +100,11 @@ def _lp(a):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads for the oracle's later parallel loops (timing only)."""
+    lib().oracle_set_threads(int(t))
 
 
 # --------------------------------------------------------------------------
@@ -149,6 +155,14 @@ def corr_ht(Y1, Y2):
     psi = np.empty((n1, n2))
     lib().oracle_corr_ht(m, n1, n2, _p(Y1), _p(Y2), _p(phi), _p(psi))
     return phi, psi
+
+
+def corr_ht_block(Y1, Y2, r0, r1, c0, c1):
+    """Rows r0..r1-1 and columns c0..c1-1 of corr_ht(Y1, Y2): the direct
+    route on those columns of the dynamic spectra (N acts on each column of
+    the second set by itself, Eq. (disHT)), for outputs too large to hold."""
+    Y1, Y2 = _f64(Y1), _f64(Y2)
+    return corr_ht(Y1[:, r0:r1], Y2[:, c0:c1])
 
 
 def corr_ht_entries(Y1, Y2, rows, cols):

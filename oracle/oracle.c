@@ -325,3 +325,14 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the parallel loops of later calls (at least 1); the CPU
+ * baseline times some sizes on one thread.                                   */
+void oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(t > 0 ? t : 1);
+#else
+    (void)t;
+#endif
+}

@@ -34,7 +34,7 @@ EXPORTED = [
     "corr2d_desc_init", "corr2d_plan", "corr2d_batched_plan", "corr2d_plan_destroy",
     "corr2d_workspace_bytes", "corr2d_plan_get_info", "corr2d_homo", "corr2d_hetero",
     "corr2d_batched", "corr2d_status_str", "corr2d_last_error", "corr2d_version",
-    "corr2d_plan_set_timing_events",
+    "corr2d_set_timing_events",
 ]
 
 
@@ -104,8 +104,8 @@ def lib():
         L.corr2d_status_str.restype = ctypes.c_char_p
         L.corr2d_last_error.argtypes = []
         L.corr2d_last_error.restype = ctypes.c_char_p
-        L.corr2d_plan_set_timing_events.argtypes = [vp, vp, vp]
-        L.corr2d_plan_set_timing_events.restype = st
+        L.corr2d_set_timing_events.argtypes = [vp, vp]
+        L.corr2d_set_timing_events.restype = st
         L.corr2d_version.argtypes = []
         L.corr2d_version.restype = ctypes.c_char_p
         _lib = L
@@ -222,8 +222,8 @@ def corr2d_plan_get_info(plan) -> corr2d_plan_info:
     return info
 
 
-def corr2d_plan_set_timing_events(plan, before, after):
-    return _check(lib().corr2d_plan_set_timing_events(plan, before, after))
+def corr2d_set_timing_events(before, after):
+    return _check(lib().corr2d_set_timing_events(before, after))
 
 
 def corr2d_homo(plan, y, ref, phi, psi, ws, ws_bytes=None, stream=None, check=True):

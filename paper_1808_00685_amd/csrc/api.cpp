@@ -25,6 +25,8 @@ using namespace corr2d;
 namespace {
 
 thread_local std::string g_last_error;
+// Measurement hook of the calling thread (corr2d_set_timing_events).
+thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
 
 corr2d_status fail(corr2d_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 corr2d_status fail(corr2d_status s, const char* fmt, ...) {
@@ -177,8 +179,11 @@ struct corr2d_plan_s {
     } key;
     bool have_graph = false;
     hipGraphExec_t gexec = nullptr;
-    hipEvent_t ev_before = nullptr, ev_after = nullptr;  // timing hook
     void* host_blob = nullptr;          // pinned host copy of the job arrays
+    // recorded on the call's stream after the last enqueued reader of
+    // host_blob (the job upload, inside the graph or not)
+    hipEvent_t blob_done = nullptr;
+    bool blob_recorded = false;
     bool blob_valid = false;
     GraphKey blob_key;
 };
@@ -677,6 +682,10 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
 corr2d_status corr2d_plan_destroy(corr2d_plan_t p) {
     if (!p) return ok();
     if (p->have_graph && p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->blob_done) {
+        if (p->blob_recorded) hipEventSynchronize(p->blob_done);
+        hipEventDestroy(p->blob_done);
+    }
     if (p->host_blob) hipHostFree(p->host_blob);
     if (p->iw_blob) hipHostFree(p->iw_blob);
     delete p;
@@ -689,10 +698,9 @@ corr2d_status corr2d_workspace_bytes(corr2d_plan_t p, size_t* bytes) {
     return ok();
 }
 
-corr2d_status corr2d_plan_set_timing_events(corr2d_plan_t p, void* before, void* after) {
-    if (!p) return fail(CORR2D_EINVAL, "NULL plan");
-    p->ev_before = (hipEvent_t)before;
-    p->ev_after = (hipEvent_t)after;
+corr2d_status corr2d_set_timing_events(void* before, void* after) {
+    g_ev_before = (hipEvent_t)before;
+    g_ev_after = (hipEvent_t)after;
     return ok();
 }
 
@@ -819,10 +827,10 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
 
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g1, p->s1, ws, phi, psi, true, p->c, p->tile,
                               p->d.ld_out, p->d.out_layout);
-    if (p->ev_before) hipEventRecord(p->ev_before, s);
+    if (g_ev_before) hipEventRecord(g_ev_before, s);
     e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
     if (e != hipSuccess) return device_fail(e, "correlation launch");
-    if (p->ev_after) hipEventRecord(p->ev_after, s);
+    if (g_ev_after) hipEventRecord(g_ev_after, s);
     return ok();
 }
 
@@ -883,10 +891,10 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
 
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g2, p->s2, ws, phi, psi, false, p->c, p->tile,
                               p->d.ld_out, CORR2D_LAYOUT_FULL);
-    if (p->ev_before) hipEventRecord(p->ev_before, s);
+    if (g_ev_before) hipEventRecord(g_ev_before, s);
     e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
     if (e != hipSuccess) return device_fail(e, "correlation launch");
-    if (p->ev_after) hipEventRecord(p->ev_after, s);
+    if (g_ev_after) hipEventRecord(g_ev_after, s);
     return ok();
 }
 
@@ -1035,6 +1043,14 @@ corr2d_status enqueue_sequential(corr2d_plan_s* p, const void* y_base, void* phi
     return CORR2D_OK;
 }
 
+// Mark the pinned job buffer as read by the work just enqueued on s.
+corr2d_status record_blob_use(corr2d_plan_s* p, hipStream_t s) {
+    hipError_t e = hipEventRecord(p->blob_done, s);
+    if (e != hipSuccess) return device_fail(e, "event record");
+    p->blob_recorded = true;
+    return ok();
+}
+
 }  // namespace
 
 extern "C" corr2d_status corr2d_batched(corr2d_plan_t p, const void* y_base, void* phi_base,
@@ -1067,11 +1083,16 @@ extern "C" corr2d_status corr2d_batched(corr2d_plan_t p, const void* y_base, voi
         hipError_t e = hipHostMalloc(&p->host_blob, L.total, hipHostMallocDefault);
         if (e != hipSuccess) { p->host_blob = nullptr; return device_fail(e, "pinned job buffer"); }
     }
+    if (!p->blob_done) {
+        hipError_t e = hipEventCreateWithFlags(&p->blob_done, hipEventDisableTiming);
+        if (e != hipSuccess) { p->blob_done = nullptr; return device_fail(e, "event creation"); }
+    }
     if (!p->blob_valid || !(p->blob_key == key)) {
-        // the previous blob may still be read by an enqueued copy
-        if (p->blob_valid) {
-            hipError_t e = hipDeviceSynchronize();
-            if (e != hipSuccess) return device_fail(e, "device synchronize");
+        // the previous blob may still be read by an enqueued copy: wait for
+        // the last call that used it (that call's stream only)
+        if (p->blob_recorded) {
+            hipError_t e = hipEventSynchronize(p->blob_done);
+            if (e != hipSuccess) return device_fail(e, "wait for the previous job upload");
         }
         fill_blob(p, y_base, phi_base, psi_base, ws);
         p->blob_valid = true;
@@ -1085,7 +1106,8 @@ extern "C" corr2d_status corr2d_batched(corr2d_plan_t p, const void* y_base, voi
 
     if (p->d.flags & CORR2D_FLAG_NO_GRAPH) {
         st = enqueue_batched(p, ws, s);
-        return st == CORR2D_OK ? ok() : st;
+        if (st != CORR2D_OK) return st;
+        return record_blob_use(p, s);
     }
     if (!p->have_graph) {
         hipStream_t cs = s;
@@ -1117,5 +1139,5 @@ extern "C" corr2d_status corr2d_batched(corr2d_plan_t p, const void* y_base, voi
     }
     hipError_t e = hipGraphLaunch(p->gexec, s);
     if (e != hipSuccess) return device_fail(e, "graph launch");
-    return ok();
+    return record_blob_use(p, s);
 }

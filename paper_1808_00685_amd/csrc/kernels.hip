@@ -1965,7 +1965,7 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
 template <int P, int TM>
 __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_kernel(CorrJob C) {
     __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
-    __shared__ int sexp[TM + 2 * kTileN2];
+    __shared__ __attribute__((aligned(16))) int sexp[TM + 2 * kTileN2];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
     if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
@@ -1979,7 +1979,7 @@ __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kerne
                                                                        int count, int64_t total,
                                                                        int* counter) {
     __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
-    __shared__ int sexp[TM + 2 * kTileN2];
+    __shared__ __attribute__((aligned(16))) int sexp[TM + 2 * kTileN2];
     __shared__ int64_t s_t;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
@@ -2009,7 +2009,7 @@ __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kerne
 template <int P, int FM, int FN>
 __global__ __launch_bounds__(256, 2) void corr_kernel(CorrJob C) {
     extern __shared__ __attribute__((aligned(16))) char corr_lds[];
-    __shared__ int sexp[32 * FM + 64 * FN];
+    __shared__ __attribute__((aligned(16))) int sexp[32 * FM + 64 * FN];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
     if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
@@ -2027,7 +2027,7 @@ __global__ __launch_bounds__(256, FM * FN < 16 ? 2 : 1) void corr_persistent_ker
                                                                int count, int64_t total,
                                                                int* counter) {
     extern __shared__ __attribute__((aligned(16))) char corr_lds[];
-    __shared__ int sexp[32 * FM + 64 * FN];
+    __shared__ __attribute__((aligned(16))) int sexp[32 * FM + 64 * FN];
     __shared__ int64_t s_t;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);

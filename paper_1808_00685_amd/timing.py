@@ -1,7 +1,7 @@
 """HIP events through libamdhip64 for kernel timing.
 
 The library records such events on the stream its kernels run on (see
-corr2d_plan_set_timing_events); torch's own events only see torch's current
+corr2d_set_timing_events); torch's own events only see torch's current
 stream.
 """
 from __future__ import annotations

@@ -85,11 +85,11 @@ def time_tile(B, torch, prec, m, n, tile, ev, reps=5):
     B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
     evs = ev.create(2 * reps)
     for r in range(reps):
-        B.corr2d_plan_set_timing_events(plan.handle, evs[2 * r], evs[2 * r + 1])
+        B.corr2d_set_timing_events(evs[2 * r], evs[2 * r + 1])
         B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
     torch.cuda.synchronize()
     ms = [ev.elapsed_ms(evs[2 * r], evs[2 * r + 1]) for r in range(reps)]
-    B.corr2d_plan_set_timing_events(plan.handle, None, None)
+    B.corr2d_set_timing_events(None, None)
     ev.destroy(evs)
     del phi, psi, ws, plan, y
     torch.cuda.empty_cache()

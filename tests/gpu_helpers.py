@@ -87,3 +87,121 @@ def check_homo_structure(phi, psi):
     assert np.array_equal(phi, phi.T)
     assert np.array_equal(psi, -psi.T)
     assert np.all(np.diag(psi) == 0)
+
+
+# ---------------------------------------------------------------------------
+# Full-matrix comparisons of outputs too large to hold twice in FP64.  The
+# arithmetic of the comparison runs in torch (FP64) on the device that holds
+# the oracle's blocks; the oracle's values themselves come from oracle/.
+# ---------------------------------------------------------------------------
+class FullError:
+    """Relative Frobenius errors ||G - O||_F / ||O||_F of Phi and Psi over the
+    full matrices, accumulated block by block, and the largest ratio of an
+    entry's error to its per-element bound (ELEMENT_TAU) seen.  For a
+    homocorrelation given as upper-triangle rows, each entry off the
+    diagonal stands for two entries of the full matrix (Phi symmetric, Psi
+    antisymmetric), so it counts twice; `diag` indexes the diagonal entries
+    of the block, which count once."""
+
+    def __init__(self):
+        self.num = [0.0, 0.0]
+        self.den = [0.0, 0.0]
+        self.bound_ratio = 0.0
+        self.entries = 0
+
+    def add(self, k, g, o, diag=None, bound=None):
+        import torch
+        g = g.to(device=o.device, dtype=torch.float64)
+        d = g - o
+        d2, o2 = d * d, o * o
+        if diag is None:
+            self.num[k] += float(d2.sum())
+            self.den[k] += float(o2.sum())
+        else:
+            self.num[k] += float(2.0 * d2.sum() - d2[diag].sum())
+            self.den[k] += float(2.0 * o2.sum() - o2[diag].sum())
+        if bound is not None:
+            err = d.abs()
+            zero_b = bound <= 0
+            # an entry whose bound is zero (a zero dynamic spectrum) must be exact
+            if bool(torch.any(err[zero_b] > 0)):
+                self.bound_ratio = float("inf")
+            r = torch.where(zero_b, torch.zeros_like(err), err / torch.where(zero_b, torch.ones_like(bound), bound))
+            if r.numel():
+                self.bound_ratio = max(self.bound_ratio, float(r.max()))
+        if k == 0:
+            self.entries += int(g.numel())
+
+    def rel(self, k):
+        if self.den[k] == 0:
+            return float(np.sqrt(self.num[k]))
+        return float(np.sqrt(self.num[k] / self.den[k]))
+
+
+def packed_rows(plane, n, r0, r1, base=0):
+    """Rows r0..r1-1 of an UPPER_PACKED plane (a torch tensor), in packed
+    order (row i: columns i..n-1), on the plane's device."""
+    s = base + r0 * n - (r0 * (r0 - 1)) // 2
+    e = base + r1 * n - (r1 * (r1 - 1)) // 2
+    return plane[s:e]
+
+
+def aligned_rows(plane, n, r0, r1):
+    """Rows r0..r1-1 of an UPPER_ALIGNED plane gathered into packed order on
+    the plane's device.  Index of (i, j) from the layout's definition:
+    i N32 - 32 (16 q (q-1) + r q) + (j - 32 q), i = 32 q + r."""
+    import torch
+    dev = plane.device
+    i = torch.arange(r0, r1, device=dev, dtype=torch.int64)
+    lens = n - i
+    rows = torch.repeat_interleave(i, lens)
+    start = torch.cumsum(lens, 0) - lens
+    j = torch.arange(rows.numel(), device=dev, dtype=torch.int64) - start[rows - r0] + rows
+    n32 = (n + 31) // 32 * 32
+    q, r = rows // 32, rows % 32
+    idx = rows * n32 - 32 * (16 * q * (q - 1) + r * q) + (j - 32 * q)
+    return plane[idx]
+
+
+def oracle_upper_blocks(oracle, S, device, block=1024, alpha=0.0):
+    """The oracle's homocorrelation (Noda's kernel and norm) as upper-triangle
+    row blocks in packed order, moved to `device` as FP64 torch tensors: list
+    of (r0, r1, phi, psi, diag, bphi, bpsi), diag the positions of the
+    diagonal entries, b* the per-element bound factors ||y_i|| ||y_j|| / (m-1)
+    (Phi) and ||y_i|| ||(N y)_j|| / (m-1) (Psi) that ELEMENT_TAU multiplies.
+    alpha scales as oracle.corr2d does."""
+    import torch
+    Y, _ = oracle.dynamic(S)
+    m, n = Y.shape
+    ny = np.linalg.norm(Y, axis=0)
+    nz = np.linalg.norm(oracle.noda_transform(Y), axis=0)
+    f = oracle.scaling_factors(oracle.band_sd(Y), alpha) if alpha else None
+    out = []
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=device)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        po, qo = oracle.corr_ht_block(Y, Y, r0, r1, r0, n)
+        mask = np.triu(np.ones((r1 - r0, n - r0), dtype=bool))
+        bp = np.outer(ny[r0:r1], ny[r0:]) / (m - 1)
+        bq = np.outer(ny[r0:r1], nz[r0:]) / (m - 1)
+        if f is not None:
+            w = np.outer(f[r0:r1], f[r0:])
+            po, qo, bp, bq = po * w, qo * w, bp * w, bq * w
+        l = np.arange(r1 - r0, dtype=np.int64)
+        diag = l * (n - r0) - (l * (l - 1)) // 2
+        out.append((r0, r1, t(po[mask]), t(qo[mask]), t(diag), t(bp[mask]), t(bq[mask])))
+        del po, qo, bp, bq, mask
+    return out
+
+
+def homo_full_error(blocks, get_rows, tau=None):
+    """FullError of a GPU homocorrelation against oracle_upper_blocks(...);
+    get_rows(k, r0, r1) returns rows r0..r1-1 of plane k (0 Phi, 1 Psi) in
+    packed order."""
+    fe = FullError()
+    for r0, r1, po, qo, diag, bp, bq in blocks:
+        for k, (o, b) in enumerate(((po, bp), (qo, bq))):
+            g = get_rows(k, r0, r1)
+            assert g.numel() == o.numel(), (g.numel(), o.numel())
+            fe.add(k, g, o, diag, None if tau is None else tau * b)
+    return fe

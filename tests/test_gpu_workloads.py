@@ -1,7 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark times, on sampled outputs the oracle computes one by one; plus the
-batched path (persistent launch replayed from a hipGraph) against sequential
-launches and the oracle.
+benchmark times: every entry of the full Phi and Psi against the oracle
+(computed in row blocks), for the m=256 x n=16384 homocorrelation, the
+m=128, 8192 x 2048 heterocorrelation and the batch of 256 data sets (the
+persistent launch replayed from a hipGraph, against sequential launches and
+the oracle).
 """
 import numpy as np
 import pytest
@@ -10,7 +12,8 @@ import oracle
 from paper_1808_00685_amd import binding as B
 from paper_1808_00685_amd import synth
 
-from .gpu_helpers import BF16_BAND_TOL, ELEMENT_TAU, TOL, packed_index, rel_fro
+from .gpu_helpers import (BF16_BAND_TOL, ELEMENT_TAU, TOL, aligned_rows, homo_full_error,
+                          oracle_upper_blocks, packed_index, packed_rows, rel_fro)
 from .lag_pairs import lag_sign_pairs
 
 pytestmark = pytest.mark.gpu
@@ -35,45 +38,45 @@ def _sample_pairs(n, count, seed, centers=()):
 
 @pytest.fixture(scope="module")
 def large():
-    S, meta = synth.workload_large()
-    i, j = _sample_pairs(S.shape[1], 6000, 3, centers=np.round(meta["centers"]).astype(int))
-    phi_o, psi_o = oracle.corr2d_entries(S, i, j)
-    Y, _ = oracle.dynamic(S)
-    ny = np.linalg.norm(Y, axis=0)
-    nz = np.linalg.norm(oracle.noda_transform(Y), axis=0)
-    return S, i, j, phi_o, psi_o, ny, nz
-
-
-@pytest.mark.parametrize("prec,basis,tol,flags", [
-    ("split_bf16", "fourier", TOL["split_bf16"], 0),
-    ("split_bf16", "fourier", TOL["split_bf16"], B.FLAG_TRANSFORM_MATMUL),
-    ("f32", "fourier", TOL["f32"], 0),
-    ("bf16", "time", BF16_BAND_TOL, 0),
-    ("bf16", "fourier", TOL["bf16"], 0),
-])
-def test_large_homo_sampled(gpu, large, prec, basis, tol, flags):
-    """m=256, n=16384 band workload, upper triangle stored (the bench's launch),
-    through the radix FFT transform (the default at this m) and, forced by the
-    flag, the table product."""
     import torch
-    S, i, j, phi_o, psi_o, ny, nz = large
+    S, meta = synth.workload_large()
+    return S, oracle_upper_blocks(oracle, S, torch.device("cuda:0"))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,basis,tol,flags,layout", [
+    ("split_bf16", "fourier", TOL["split_bf16"], 0, "upper_aligned"),
+    ("split_bf16", "fourier", TOL["split_bf16"], B.FLAG_TRANSFORM_MATMUL, "upper_packed"),
+    ("f32", "fourier", TOL["f32"], 0, "upper_aligned"),
+    ("bf16", "time", BF16_BAND_TOL, 0, "upper_aligned"),
+    ("bf16", "fourier", BF16_BAND_TOL, 0, "upper_aligned"),
+])
+def test_large_homo_full(gpu, large, prec, basis, tol, flags, layout):
+    """m=256, n=16384 band workload, upper triangle stored (the bench's
+    launch), through the radix FFT transform (the default at this m) and,
+    forced by the flag, the table product: every entry of the full Phi and
+    Psi against the oracle (relative Frobenius error over the full matrix,
+    and each entry within its own bound, gpu_helpers.ELEMENT_TAU)."""
+    import torch
+    S, blocks = large
     n = S.shape[1]
     phi, psi, plan, ws = B.homo(torch.as_tensor(S, device=gpu), prec=prec, basis=basis,
-                                layout="upper_packed", flags=flags)
+                                layout=layout, flags=flags)
+    torch.cuda.synchronize()
     assert B.corr2d_plan_get_info(plan.handle).transform == (0 if flags else 1)
-    idx = torch.as_tensor(packed_index(i, j, n), device=gpu)
-    g_phi = phi[idx].double().cpu().numpy()
-    g_psi = psi[idx].double().cpu().numpy()
-    e_phi, e_psi = rel_fro(g_phi, phi_o), rel_fro(g_psi, psi_o)
-    print(f"large {prec}/{basis}/flags={flags}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
+    rows = aligned_rows if layout == "upper_aligned" else packed_rows
+    planes = (phi, psi)
+    fe = homo_full_error(blocks, lambda k, r0, r1: rows(planes[k], n, r0, r1),
+                         tau=ELEMENT_TAU[prec])
+    e_phi, e_psi = fe.rel(0), fe.rel(1)
+    print(f"large {prec}/{basis}/flags={flags}/{layout}: full-matrix rel.err phi={e_phi:.3e} "
+          f"psi={e_psi:.3e} (largest error/bound {fe.bound_ratio:.3f})")
+    assert fe.entries == n * (n + 1) // 2
     assert e_phi <= tol and e_psi <= tol
-    # every sampled entry within its own bound (see gpu_helpers.ELEMENT_TAU)
-    m = S.shape[0]
-    tau = ELEMENT_TAU[prec]
-    assert np.all(np.abs(g_phi - phi_o) <= tau * ny[i] * ny[j] / (m - 1))
-    assert np.all(np.abs(g_psi - psi_o) <= tau * ny[i] * nz[j] / (m - 1))
-    d = torch.as_tensor(packed_index(np.arange(n), np.arange(n), n), device=gpu)
-    assert torch.all(psi[d] == 0)
+    assert fe.bound_ratio <= 1.0
+    ii = np.arange(n)
+    d = packed_index(ii, ii, n) if layout == "upper_packed" else B.upper_aligned_index(ii, ii, n)
+    assert torch.all(psi[torch.as_tensor(d, device=gpu)] == 0)
     del phi, psi, ws
 
 
@@ -121,45 +124,43 @@ def test_large_upper_aligned_equals_packed(gpu, large):
 @pytest.fixture(scope="module")
 def hetero_data():
     S1, S2, meta = synth.workload_hetero()
+    Y1, Y2 = oracle.dynamic(S1)[0], oracle.dynamic(S2)[0]
+    phi_o, psi_o = oracle.corr_ht(Y1, Y2)
     c1 = np.round(meta["set1"]["centers"]).astype(int)
     c2 = np.round(meta["set2"]["centers"]).astype(int)
-    rng = np.random.default_rng(4)
-    i = np.concatenate([rng.integers(0, S1.shape[1], 5000), np.repeat(c1, len(c2))])
-    j = np.concatenate([rng.integers(0, S2.shape[1], 5000), np.tile(c2, len(c1))])
-    phi_o, psi_o = oracle.corr2d_entries(S1, i, j, S2=S2)
-    Y1, Y2 = oracle.dynamic(S1)[0], oracle.dynamic(S2)[0]
     norms = (np.linalg.norm(Y1, axis=0), np.linalg.norm(Y2, axis=0),
              np.linalg.norm(oracle.noda_transform(Y2), axis=0))
-    return S1, S2, meta, i, j, phi_o, psi_o, len(c1) * len(c2), norms
+    return S1, S2, meta, phi_o, psi_o, c1, c2, norms
 
 
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("prec", ["f16", "fp8_e4m3", "split_bf16"])
-def test_hetero_workload_sampled(gpu, hetero_data, prec):
-    """m=128, 8192 x 2048 heterocorrelation with per-band scaling."""
+def test_hetero_workload_full(gpu, hetero_data, prec):
+    """m=128, 8192 x 2048 heterocorrelation with per-band scaling: every
+    entry against the oracle."""
     import torch
-    S1, S2, meta, i, j, phi_o, psi_o, ncoupled, (ny1, ny2, nz2) = hetero_data
+    S1, S2, meta, phi_o, psi_o, c1, c2, (ny1, ny2, nz2) = hetero_data
     phi, psi, plan, ws = B.hetero(torch.as_tensor(S1, device=gpu), torch.as_tensor(S2, device=gpu),
                                   prec=prec)
     if prec in ("f16", "fp8_e4m3"):
         assert plan.info.per_band_scale == 1
-    ti, tj = torch.as_tensor(i, device=gpu), torch.as_tensor(j, device=gpu)
-    g_phi = phi[ti, tj].double().cpu().numpy()
-    g_psi = psi[ti, tj].double().cpu().numpy()
+    g_phi = phi.double().cpu().numpy()
+    g_psi = psi.double().cpu().numpy()
     e_phi, e_psi = rel_fro(g_phi, phi_o), rel_fro(g_psi, psi_o)
-    print(f"hetero {prec}: sampled rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
+    print(f"hetero {prec}: full-matrix rel.err phi={e_phi:.3e} psi={e_psi:.3e}")
     assert e_phi <= TOL[prec] and e_psi <= TOL[prec]
-    # every sampled entry within its own bound (gpu_helpers.ELEMENT_TAU)
+    # every entry within its own bound (gpu_helpers.ELEMENT_TAU)
     m, tau = S1.shape[0], ELEMENT_TAU[prec]
-    assert np.all(np.abs(g_phi - phi_o) <= tau * ny1[i] * ny2[j] / (m - 1))
-    assert np.all(np.abs(g_psi - psi_o) <= tau * ny1[i] * nz2[j] / (m - 1))
+    assert np.all(np.abs(g_phi - phi_o) <= tau * np.outer(ny1, ny2) / (m - 1))
+    assert np.all(np.abs(g_psi - psi_o) <= tau * np.outer(ny1, nz2) / (m - 1))
     # sign of Psi at band-centre pairs agrees with the oracle where it is not tiny
-    sel = slice(len(i) - ncoupled, len(i))
-    big = np.abs(psi_o[sel]) > 0.05 * np.abs(psi_o[sel]).max()
-    assert np.all(np.sign(g_psi[sel][big]) == np.sign(psi_o[sel][big]))
+    cq, cg = psi_o[np.ix_(c1, c2)], g_psi[np.ix_(c1, c2)]
+    big = np.abs(cq) > 0.05 * np.abs(cq).max()
+    assert np.all(np.sign(cg[big]) == np.sign(cq[big]))
     # and with the generator's driver lags where those fix it
     li, lj, expected = lag_sign_pairs(meta)
-    lag = psi[torch.as_tensor(li, device=gpu), torch.as_tensor(lj, device=gpu)].double().cpu().numpy()
-    assert np.all(np.sign(lag) == expected)
+    assert np.all(np.sign(g_psi[li, lj]) == expected)
+    del phi, psi, ws
 
 
 def _batch(count, seed, n_range):
@@ -225,6 +226,50 @@ def test_batched_graph_matches_sequential_and_oracle(gpu, prec):
         tau = ELEMENT_TAU[prec]
         assert np.all(np.abs(gp[pidx] - po) <= tau * ny[i] * ny[j] / (it.m - 1)), k
         assert np.all(np.abs(gq[pidx] - qo) <= tau * ny[i] * nz[j] / (it.m - 1)), k
+
+
+@pytest.mark.timeout(1200)
+def test_batched_full_size_every_set(gpu):
+    """The batch of 256 data sets at its real size (m in 8..200, n in
+    256..8192; the bench's launch): the graph-replayed persistent launch in
+    FP32 and split-BF16, every data set's full Phi and Psi against the oracle
+    at 1e-5 (relative Frobenius over each full matrix) and every entry within
+    its own bound; FP32 sequential launches give the same bits."""
+    import time as _time
+    import torch
+    items = synth.batch_spec()
+    data = [synth.batch_item_data(it) for it in items]
+    outs = {}
+    for name, prec, flags in (("graph", "f32", 0), ("split", "split_bf16", 0),
+                              ("sequential", "f32", B.FLAG_SEQUENTIAL)):
+        plan, y, phi, psi, ws, ooffs = _run_batched(gpu, items, data, prec, flags)
+        B.corr2d_batched(plan.handle, y, phi, psi, ws)
+        torch.cuda.synchronize()
+        outs[name] = (phi, psi)
+        del plan, ws, y
+    assert torch.equal(outs["graph"][0], outs["sequential"][0])
+    assert torch.equal(outs["graph"][1], outs["sequential"][1])
+    del outs["sequential"]
+    worst = {}
+    t0 = _time.time()
+    for k, (it, S, oo) in enumerate(zip(items, data, ooffs)):
+        blocks = oracle_upper_blocks(oracle, S, gpu)
+        for name, prec in (("graph", "f32"), ("split", "split_bf16")):
+            planes = outs[name]
+            fe = homo_full_error(blocks, lambda q, r0, r1: packed_rows(planes[q], it.n, r0, r1, oo),
+                                 tau=ELEMENT_TAU[prec])
+            assert fe.entries == it.n * (it.n + 1) // 2
+            e = (fe.rel(0), fe.rel(1), fe.bound_ratio)
+            if name not in worst or max(e[:2]) > max(worst[name][1][:2]):
+                worst[name] = (k, e)
+            assert e[0] <= TOL[prec] and e[1] <= TOL[prec], (name, k, it.m, it.n, e)
+            assert e[2] <= 1.0, (name, k, it.m, it.n, e)
+        del blocks
+        if k % 32 == 31:
+            print(f"batch: {k + 1} sets compared ({_time.time() - t0:.0f} s)", flush=True)
+    for name, (k, e) in worst.items():
+        print(f"batch {name}: worst set {k} (m={items[k].m}, n={items[k].n}) rel.err "
+              f"phi={e[0]:.3e} psi={e[1]:.3e}, largest error/bound {e[2]:.3f}")
 
 
 def test_batched_full_layout_and_no_graph(gpu):

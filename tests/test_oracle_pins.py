@@ -532,3 +532,15 @@ def test_interpolation_small_cases_and_linear():
     Se = np.random.default_rng(4).standard_normal((6, 3))
     for meth in ("linear", "spline"):
         assert np.allclose(oracle.interpolate(Se, te, 6, meth), Se, atol=1e-13)
+
+
+def test_corr_ht_block_is_the_block_of_the_full_result():
+    """The row/column block helper (used where the full output is too large
+    to hold) returns exactly that block of the direct route: N acts on each
+    column of the second set by itself, so slicing before is slicing after."""
+    rng = np.random.default_rng(11)
+    Y1, Y2 = rng.standard_normal((13, 50)), rng.standard_normal((13, 37))
+    p, q = oracle.corr_ht(Y1, Y2)
+    for r0, r1, c0, c1 in ((0, 50, 0, 37), (7, 19, 3, 30), (49, 50, 36, 37)):
+        bp, bq = oracle.corr_ht_block(Y1, Y2, r0, r1, c0, c1)
+        assert np.array_equal(bp, p[r0:r1, c0:c1]) and np.array_equal(bq, q[r0:r1, c0:c1])
