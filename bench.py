@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("correlation entries/s and MFMA TFLOP/s at stated error vs oracle; "
           "split vs plain")
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "split_bf16": 2500.0, "bf16": 2500.0,
-               "f16": 2500.0, "fp8_e4m3": 5000.0}
+               "f16": 2500.0, "fp8_e4m3": 5000.0, "split_f16": 2500.0}
 HBM_GBPS = 8000.0
 
 
@@ -219,11 +219,12 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, ref,
     entries = n * (n + 1) // 2
     alg_flops = 4.0 * m * entries
     executed = 2.0 * 2.0 * info.tiles * info.tile_m * info.tile_n * info.k_pad
-    if prec == "split_bf16":
+    if prec in ("split_bf16", "split_f16"):
         executed *= 3
     kernel_ms = float(np.mean(kms))
     esz = 8 if out_dtype == "f64" else 4
-    planes = {"f64": 8, "f32": 4, "split_bf16": 4, "bf16": 2, "f16": 2, "fp8_e4m3": 1}[prec]
+    planes = {"f64": 8, "f32": 4, "split_bf16": 4, "bf16": 2, "f16": 2, "fp8_e4m3": 1,
+              "split_f16": 4}[prec]
     kernel_bytes = 2 * entries * esz + 2 * n * info.k_pad * planes
     res = {
         "prec": prec, "basis": basis, "scale_alpha": alpha, "layout": layout,
@@ -494,7 +495,7 @@ def batch_workload(B, torch, oracle, synth, dev, otimes):
     spec = [(it.m, it.n, o, 0, oo) for it, o, oo in zip(items, offs, ooffs)]
     res, outs = {}, {}
     for name, prec, flags in (("graph", "f32", 0), ("sequential", "f32", B.FLAG_SEQUENTIAL),
-                              ("split", "split_bf16", 0)):
+                              ("split", "split_bf16", 0), ("split16", "split_f16", 0)):
         if name != "sequential":
             outs[name] = (torch.empty(ocur, dtype=torch.float32, device=dev),
                           torch.empty(ocur, dtype=torch.float32, device=dev))
@@ -530,7 +531,8 @@ def batch_workload(B, torch, oracle, synth, dev, otimes):
                    "seconds": osecs, "entries_per_s": entries / osecs})
     desc = f"batch of {len(items)} homocorrelations, m in 8..200, n in 256..8192, "
     rows = []
-    for name, prec, text in (("graph", "f32", "FP32"), ("split", "split_bf16", "split-BF16")):
+    for name, prec, text in (("graph", "f32", "FP32"), ("split", "split_bf16", "split-BF16"),
+                             ("split16", "split_f16", "split-FP16")):
         a, w = agg[name], worst[name]
         r = {"workload": desc + text + ", upper triangles", "prec": prec,
              "ms_per_call": res[name], "entries_per_s": entries / (res[name] * 1e-3),
@@ -605,8 +607,8 @@ def main():
         other = "upper_packed" if layout == "upper_aligned" else "upper_aligned"
         variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, ref,
                                     layout=other))
-        for prec, basis in (("f32", "fourier"), ("bf16", "fourier"), ("bf16", "time"),
-                            ("f64", "fourier")):
+        for prec, basis in (("split_f16", "fourier"), ("f32", "fourier"), ("bf16", "fourier"),
+                            ("bf16", "time"), ("f64", "fourier")):
             variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, ref,
                                         layout=layout))
         # Pareto scaling (alpha = 0.5) of the headline form: the oracle's

@@ -85,7 +85,11 @@ typedef enum corr2d_prec {
     CORR2D_PREC_SPLIT_BF16 = 2, /* x = hi + lo (both BF16); hi*hi+hi*lo+lo*hi   */
     CORR2D_PREC_BF16 = 3,       /* plain BF16                                   */
     CORR2D_PREC_F16 = 4,        /* FP16, per-band scaling on by default          */
-    CORR2D_PREC_FP8_E4M3 = 5    /* OCP FP8 e4m3, per-band scaling required      */
+    CORR2D_PREC_FP8_E4M3 = 5,   /* OCP FP8 e4m3, per-band scaling required      */
+    CORR2D_PREC_SPLIT_F16 = 6   /* x = hi + lo (both FP16) after the per-band
+                                   power-of-two scale (required); hi*hi+hi*lo+
+                                   lo*hi: 11-bit halves, per-product error
+                                   about 2^-22 against split BF16's 2^-16     */
 } corr2d_prec;
 
 /* Basis of the contraction.  FOURIER contracts the real-packed Hermitian half
@@ -93,7 +97,14 @@ typedef enum corr2d_prec {
  * directly (the paper's Hilbert-transform route).  Both give the same Phi and
  * Psi up to rounding; they differ in how rounding errors of reduced precisions
  * accumulate.                                                                 */
-typedef enum corr2d_basis { CORR2D_BASIS_FOURIER = 0, CORR2D_BASIS_TIME = 1 } corr2d_basis;
+typedef enum corr2d_basis {
+    CORR2D_BASIS_FOURIER = 0,
+    CORR2D_BASIS_TIME = 1,
+    CORR2D_BASIS_AUTO = 2   /* the default: TIME for plain BF16 (its rounding
+                               errors then spread over all m products instead
+                               of concentrating in the few Fourier rows that
+                               carry the bands), FOURIER otherwise            */
+} corr2d_basis;
 typedef enum corr2d_hilbert {
     CORR2D_HILBERT_NODA = 0,      /* Noda's matrix, Eq. (HilbNoda)                   */
     CORR2D_HILBERT_CIRCULAR = 1,  /* m-point route, Hermitian-complete half spectrum */
@@ -211,7 +222,7 @@ typedef struct corr2d_plan_info {
     int64_t out_elements; /* batched plans: elements of phi (and of psi) written  */
     int32_t transform;    /* perturbation-axis transform: 0 = product with the DFT
                              table on MFMA, 1 = radix FFT in LDS                  */
-    int32_t reserved;
+    int32_t basis;        /* corr2d_basis in use (AUTO resolved)                  */
     /* Single and hetero plans: byte offsets in the workspace of the reference
      * spectra a call subtracts (Sec. 2 Eqs. (dynspec), (ref); the Ref1 and
      * Ref2 of the paper's result object, Sec. 3): n1 (n2) doubles, the
@@ -223,7 +234,7 @@ typedef struct corr2d_plan_info {
     size_t ref2_offset;
 } corr2d_plan_info;
 
-/* Fill *d with defaults: FP64 input, FP32 output, SPLIT_BF16, FOURIER, NODA
+/* Fill *d with defaults: FP64 input, FP32 output, SPLIT_BF16, AUTO basis, NODA
  * kernel and norm, FULL layout, automatic tile.  The caller sets m, n1, n2.  */
 void corr2d_desc_init(corr2d_desc* d);
 

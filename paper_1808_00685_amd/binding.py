@@ -16,8 +16,8 @@ LIB_PATH = os.path.join(HERE, "libcorr2d.so")
 
 # enums of corr2d.h
 OK, EINVAL, EWORKSPACE, EUNSUPPORTED, EDEVICE, ENOMEM = range(6)
-PREC = {"f64": 0, "f32": 1, "split_bf16": 2, "bf16": 3, "f16": 4, "fp8_e4m3": 5}
-BASIS = {"fourier": 0, "time": 1}
+PREC = {"f64": 0, "f32": 1, "split_bf16": 2, "bf16": 3, "f16": 4, "fp8_e4m3": 5, "split_f16": 6}
+BASIS = {"fourier": 0, "time": 1, "auto": 2}
 HILBERT = {"noda": 0, "circular": 1, "r_compat": 2}
 INTERP = {"none": 0, "linear": 1, "spline": 2}
 NORM = {"noda": 0, "paper": 1, "custom": 2}
@@ -63,7 +63,7 @@ class corr2d_plan_info(ctypes.Structure):
         ("tile", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32),
         ("per_band_scale", ctypes.c_int32), ("c", ctypes.c_double),
         ("workspace_bytes", ctypes.c_size_t), ("items", ctypes.c_int64),
-        ("out_elements", ctypes.c_int64), ("transform", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("out_elements", ctypes.c_int64), ("transform", ctypes.c_int32), ("basis", ctypes.c_int32),
         ("ref1_offset", ctypes.c_size_t), ("ref2_offset", ctypes.c_size_t),
     ]
 
@@ -303,7 +303,7 @@ def out_elements(layout, n1, n2=0):
     return n1 * (n2 or n1)
 
 
-def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="fourier",
+def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="auto",
          hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0,
          t_in=None, interp="none", m_out=None, stream=None):
     """Homocorrelation of y (torch, m x n, float64/float32, on the GPU).  With
@@ -331,7 +331,7 @@ def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="f
     return phi, psi, plan, ws
 
 
-def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basis="fourier",
+def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basis="auto",
            hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0,
            t_in=None, interp="none", m_out=None, stream=None):
     """Heterocorrelation of y1 (m x n1) with y2 (m x n2), both on the GPU;

@@ -195,10 +195,10 @@ bool valid_enum(int v, int lo, int hi) { return v >= lo && v <= hi; }
 corr2d_status check_common(const corr2d_desc* d) {
     if (!valid_enum(d->in_dtype, 0, 1) || !valid_enum(d->out_dtype, 0, 1))
         return fail(CORR2D_EINVAL, "in_dtype/out_dtype must be CORR2D_DTYPE_F64 or _F32");
-    if (!valid_enum(d->prec, 0, 5)) return fail(CORR2D_EINVAL, "unknown prec %d", d->prec);
-    if (!valid_enum(d->basis, 0, 1)) return fail(CORR2D_EINVAL, "unknown basis %d", d->basis);
+    if (!valid_enum(d->prec, 0, 6)) return fail(CORR2D_EINVAL, "unknown prec %d", d->prec);
+    if (!valid_enum(d->basis, 0, 2)) return fail(CORR2D_EINVAL, "unknown basis %d", d->basis);
     if (!valid_enum(d->hilbert, 0, 2)) return fail(CORR2D_EINVAL, "unknown hilbert %d", d->hilbert);
-    if (d->hilbert == CORR2D_HILBERT_R_COMPAT && d->basis != CORR2D_BASIS_FOURIER)
+    if (d->hilbert == CORR2D_HILBERT_R_COMPAT && d->basis == CORR2D_BASIS_TIME)
         return fail(CORR2D_EUNSUPPORTED, "the R-compatible bin list needs the Fourier basis");
     if (!valid_enum(d->norm_mode, 0, 2)) return fail(CORR2D_EINVAL, "unknown norm_mode %d", d->norm_mode);
     if (!valid_enum(d->out_layout, 0, 2)) return fail(CORR2D_EINVAL, "unknown out_layout %d", d->out_layout);
@@ -220,6 +220,8 @@ corr2d_status check_common(const corr2d_desc* d) {
     if (d->flags & ~0x1fu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
     if (d->prec == CORR2D_PREC_FP8_E4M3 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
         return fail(CORR2D_EUNSUPPORTED, "FP8 e4m3 requires per-band scaling (range 448)");
+    if (d->prec == CORR2D_PREC_SPLIT_F16 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
+        return fail(CORR2D_EUNSUPPORTED, "split FP16 requires per-band scaling (range 65504)");
     if (d->tile < 0 || d->tile > 3)
         return fail(CORR2D_EINVAL, "unknown tile id %d", d->tile);
     if (d->tile == 3 && !blocked_layout(d->prec))
@@ -227,6 +229,17 @@ corr2d_status check_common(const corr2d_desc* d) {
     if (d->tile == 1 && blocked_layout(d->prec))
         return fail(CORR2D_EUNSUPPORTED, "tile 1 (64x64) is not built for the 16-bit formats");
     return CORR2D_OK;
+}
+
+// CORR2D_BASIS_AUTO: the time basis for plain BF16, whose single rounding
+// of each operand then spreads over all m products of a sum instead of
+// concentrating in the few Fourier rows that carry the bands (a measured
+// 7x smaller error on band spectra); the Fourier basis otherwise, and
+// wherever the kernel needs it (the R bin list).
+int resolve_basis(const corr2d_desc* d) {
+    if (d->basis != CORR2D_BASIS_AUTO) return d->basis;
+    if (d->prec == CORR2D_PREC_BF16 && d->hilbert != CORR2D_HILBERT_R_COMPAT) return CORR2D_BASIS_TIME;
+    return CORR2D_BASIS_FOURIER;
 }
 
 double norm_cF(const corr2d_desc* d, int64_t m) {
@@ -254,6 +267,9 @@ void set_scaling(corr2d_plan_s* p) {
     } else if (prec == CORR2D_PREC_F16) {
         p->scale = !(p->d.flags & CORR2D_FLAG_NO_PER_BAND_SCALE);
         p->qhalf = 32752.0f;
+    } else if (prec == CORR2D_PREC_SPLIT_F16) {
+        p->scale = true;
+        p->qhalf = 32752.0f;
     }
 }
 
@@ -262,13 +278,16 @@ double bound_a(const corr2d_desc* d, int64_t m) {
 }
 
 // Layout of one data set's workspace regions, appended at *off.
-SetLayout layout_set(const Geo& g, int prec, bool t64, bool need_b, size_t* off) {
+// The centred spectra (yt) are needed by the table-product transform only;
+// the radix FFT transform centres in registers and LDS (need_yt false).
+SetLayout layout_set(const Geo& g, int prec, bool t64, bool need_b, bool need_yt, size_t* off) {
     SetLayout s;
     const size_t tsz = t64 ? 8 : 4;
     const size_t esz = (size_t)elem_bytes(prec);
     const size_t plane = (size_t)g.n_pad * g.kp * esz;
     s.ref = *off; *off = align256(*off + (size_t)g.n_pad * sizeof(double));
-    s.yt = *off; *off = align256(*off + (size_t)g.n_pad * g.kt * tsz);
+    s.yt = *off;
+    if (need_yt) *off = align256(*off + (size_t)g.n_pad * g.kt * tsz);
     s.sA = *off; *off = align256(*off + (size_t)g.n_pad * 4);
     s.A0 = *off; *off = align256(*off + plane);
     if (planes(prec) == 2) { s.A1 = *off; *off = align256(*off + plane); }
@@ -379,8 +398,8 @@ bool log_enabled() {
 }
 
 const char* prec_name(int prec) {
-    static const char* names[] = {"f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"};
-    return prec >= 0 && prec < 6 ? names[prec] : "?";
+    static const char* names[] = {"f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3", "split_f16"};
+    return prec >= 0 && prec < 7 ? names[prec] : "?";
 }
 
 // Table-product plans with m <= kPrepMergeMaxM build the table and centre
@@ -468,7 +487,7 @@ void corr2d_desc_init(corr2d_desc* d) {
     d->in_dtype = CORR2D_DTYPE_F64;
     d->out_dtype = CORR2D_DTYPE_F32;
     d->prec = CORR2D_PREC_SPLIT_BF16;
-    d->basis = CORR2D_BASIS_FOURIER;
+    d->basis = CORR2D_BASIS_AUTO;
     d->hilbert = CORR2D_HILBERT_NODA;
     d->norm_mode = CORR2D_NORM_NODA;
     d->out_layout = CORR2D_LAYOUT_FULL;
@@ -513,12 +532,13 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     corr2d_plan_s* p = new (std::nothrow) corr2d_plan_s;
     if (!p) return fail(CORR2D_ENOMEM, "host allocation of the plan failed");
     p->d = *d;
+    p->d.basis = resolve_basis(d);
     p->d.ld_in1 = ld1;
     p->d.ld_in2 = hetero ? ld2 : 0;
     p->d.ld_out = ldo;
     p->hetero = hetero;
     set_scaling(p);
-    p->c = contraction_factor(d, d->m);
+    p->c = contraction_factor(&p->d, d->m);
     p->tile = choose_tile(d, d->m, hetero ? std::max(d->n1, d->n2) : d->n1);
     if (!corr_variant_supported(d->prec, p->tile.fm, p->tile.fn)) {
         delete p;
@@ -526,18 +546,18 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     }
     const bool t64 = d->prec == CORR2D_PREC_F64;
     p->g1 = geometry(d->m, d->n1, d->prec);
-    p->fft = use_fft(d, d->m);
+    p->fft = use_fft(&p->d, d->m);
     size_t off = 0;
     p->table_off = off;
     off = align256(off + table_bytes(p->g1, t64));
     if (!hetero) {
-        p->s1 = layout_set(p->g1, d->prec, t64, true, &off);
+        p->s1 = layout_set(p->g1, d->prec, t64, true, !p->fft, &off);
         const int64_t T = p->g1.n_pad / (32 * p->tile.fm);
         p->ntiles = triangle_tiles(T, p->tile.fm / p->tile.fn);
     } else {
         p->g2 = geometry(d->m, d->n2, d->prec);
-        p->s1 = layout_set(p->g1, d->prec, t64, false, &off);
-        p->s2 = layout_set(p->g2, d->prec, t64, true, &off);
+        p->s1 = layout_set(p->g1, d->prec, t64, false, !p->fft, &off);
+        p->s2 = layout_set(p->g2, d->prec, t64, true, !p->fft, &off);
         p->ntiles = (p->g1.n_pad / (32 * p->tile.fm)) * (p->g2.n_pad / (32 * p->tile.fn));
     }
     if (d->interp != CORR2D_INTERP_NONE) {
@@ -591,6 +611,7 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
     corr2d_plan_s* p = new (std::nothrow) corr2d_plan_s;
     if (!p) return fail(CORR2D_ENOMEM, "host allocation of the plan failed");
     p->d = *common;
+    p->d.basis = resolve_basis(common);
     p->batched = true;
     set_scaling(p);
     const bool t64 = common->prec == CORR2D_PREC_F64;
@@ -611,10 +632,10 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
         I.it = items[i];
         if (I.it.ld_in == 0) I.it.ld_in = I.it.n;
         I.g = geometry(I.it.m, I.it.n, common->prec);
-        I.s = layout_set(I.g, common->prec, t64, true, &off);
+        I.s = layout_set(I.g, common->prec, t64, true, true, &off);
         const size_t mi = std::find(p->distinct_m.begin(), p->distinct_m.end(), I.it.m) - p->distinct_m.begin();
         I.table_off = p->table_of_m[mi];
-        I.c = contraction_factor(common, I.it.m);
+        I.c = contraction_factor(&p->d, I.it.m);
         // each data set takes the tuned tile shape for its own m and n
         I.tile = choose_tile(common, I.it.m, I.it.n);
         if (!corr_variant_supported(common->prec, I.tile.fm, I.tile.fn)) {
@@ -725,6 +746,7 @@ corr2d_status corr2d_plan_get_info(corr2d_plan_t p, corr2d_plan_info* info) {
         info->tiles = p->ntiles;
         info->c = p->c;
         info->transform = p->fft ? 1 : 0;
+        info->basis = p->d.basis;
         info->ref1_offset = p->s1.ref;
         info->ref2_offset = p->hetero ? p->s2.ref : p->s1.ref;
     }

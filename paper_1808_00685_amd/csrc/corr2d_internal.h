@@ -5,7 +5,7 @@
 
 namespace corr2d {
 
-enum Prec : int { P_F64 = 0, P_F32 = 1, P_SPLIT = 2, P_BF16 = 3, P_F16 = 4, P_FP8 = 5 };
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_SPLIT = 2, P_BF16 = 3, P_F16 = 4, P_FP8 = 5, P_SPLIT16 = 6 };
 enum Basis : int { B_FOURIER = 0, B_TIME = 1 };
 enum Hilbert : int { H_NODA = 0, H_CIRCULAR = 1, H_R_COMPAT = 2 };
 enum Layout : int { L_FULL = 0, L_UPPER = 1, L_UPPER_ALIGNED = 2 };
@@ -14,7 +14,7 @@ enum Layout : int { L_FULL = 0, L_UPPER = 1, L_UPPER_ALIGNED = 2 };
 // operand layout (see blocked_index); the others the register-direct kernel
 // and the row layout [i][kp].
 __host__ __device__ constexpr bool blocked_layout(int prec) {
-    return prec == P_SPLIT || prec == P_BF16 || prec == P_F16;
+    return prec == P_SPLIT || prec == P_BF16 || prec == P_F16 || prec == P_SPLIT16;
 }
 
 // Contraction length granularity per precision (the LDS-staged kernel of
@@ -40,7 +40,7 @@ __host__ __device__ constexpr int64_t blocked_index(int64_t i, int64_t k, int64_
 __host__ __device__ constexpr int elem_bytes(int prec) {
     return prec == P_F64 ? 8 : prec == P_F32 ? 4 : prec == P_FP8 ? 1 : 2;
 }
-__host__ __device__ constexpr int planes(int prec) { return prec == P_SPLIT ? 2 : 1; }
+__host__ __device__ constexpr int planes(int prec) { return prec == P_SPLIT || prec == P_SPLIT16 ? 2 : 1; }
 
 constexpr int kTransformK = 16;   // inner-dimension granularity of the transform GEMM
 constexpr int kTransformTile = 64;

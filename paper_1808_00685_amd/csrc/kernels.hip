@@ -68,6 +68,18 @@ __device__ inline void bf16x2_split(float a, float b, uint32_t& hi, uint32_t& lo
     lo = bf16x2_rne(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
 }
 
+// Split of four floats into FP16 halves: hi = RNE(x), lo = RNE(x - hi) (x - hi
+// is exact in FP32 while |x| stays within the FP16 range, which the per-band
+// scales guarantee).
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+__device__ inline void f16x4_split(const float* x, h4v& hi, h4v& lo) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        hi[q] = (_Float16)x[q];
+        lo[q] = (_Float16)(x[q] - (float)hi[q]);
+    }
+}
+
 // float -> OCP FP8 e4m3 (bias 7, 3 mantissa bits, largest finite 448, no
 // infinities), round to nearest even, saturating at +-448; NaN -> 0x7f.
 __device__ inline uint8_t fp8_e4m3_rne(float x) {
@@ -530,8 +542,12 @@ __device__ inline void store_operand4(void* p0, void* p1, int64_t idx, const flo
         *(uint2*)((uint16_t*)p0 + idx) = make_uint2(hw[0], hw[1]);
         if constexpr (P == P_SPLIT) *(uint2*)((uint16_t*)p1 + idx) = make_uint2(lw[0], lw[1]);
     } else if constexpr (P == P_F16) {
-        typedef _Float16 h4v __attribute__((ext_vector_type(4)));
         *(h4v*)((_Float16*)p0 + idx) = h4v{(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3]};
+    } else if constexpr (P == P_SPLIT16) {
+        h4v hi, lo;
+        f16x4_split(x, hi, lo);
+        *(h4v*)((_Float16*)p0 + idx) = hi;
+        *(h4v*)((_Float16*)p1 + idx) = lo;
     } else if constexpr (P == P_FP8) {
         *(uint32_t*)((uint8_t*)p0 + idx) = fp8_e4m3_rne(x[0]) | ((uint32_t)fp8_e4m3_rne(x[1]) << 8) |
                                            ((uint32_t)fp8_e4m3_rne(x[2]) << 16) | ((uint32_t)fp8_e4m3_rne(x[3]) << 24);
@@ -1029,6 +1045,12 @@ __device__ inline void store_operand8(void* p0, void* p1, int64_t idx, const S (
     } else if constexpr (P == P_F16) {
         *(h8*)((_Float16*)p0 + idx) = h8{(_Float16)x[0], (_Float16)x[1], (_Float16)x[2], (_Float16)x[3],
                                          (_Float16)x[4], (_Float16)x[5], (_Float16)x[6], (_Float16)x[7]};
+    } else if constexpr (P == P_SPLIT16) {
+        h4v h0, l0, h1, l1;
+        f16x4_split(x, h0, l0);
+        f16x4_split(x + 4, h1, l1);
+        *(h8*)((_Float16*)p0 + idx) = h8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+        *(h8*)((_Float16*)p1 + idx) = h8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
     } else if constexpr (P == P_FP8) {
         uint32_t w[2];
 #pragma unroll
@@ -1217,6 +1239,7 @@ template <> struct Frag<P_F32> { using T = f4; using Acc = f4; static constexpr 
 template <> struct Frag<P_SPLIT> { using T = bf8; using Acc = f4; static constexpr int KS = 32; };
 template <> struct Frag<P_BF16> { using T = bf8; using Acc = f4; static constexpr int KS = 32; };
 template <> struct Frag<P_F16> { using T = h8; using Acc = f4; static constexpr int KS = 32; };
+template <> struct Frag<P_SPLIT16> { using T = h8; using Acc = f4; static constexpr int KS = 32; };
 template <> struct Frag<P_FP8> { using T = u4; using Acc = f4; static constexpr int KS = 64; };
 
 template <int P>
@@ -1238,7 +1261,7 @@ __device__ inline void mma(typename Frag<P>::Acc& acc, const typename Frag<P>::T
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
     } else if constexpr (P == P_SPLIT || P == P_BF16) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    } else if constexpr (P == P_F16) {
+    } else if constexpr (P == P_F16 || P == P_SPLIT16) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
     } else {
         const long a0 = (long)a[0] | ((long)a[1] << 32), a1 = (long)a[2] | ((long)a[3] << 32);
@@ -1682,10 +1705,11 @@ template <int P> struct Wide;
 template <> struct Wide<P_SPLIT> { using T = bf8; };
 template <> struct Wide<P_BF16> { using T = bf8; };
 template <> struct Wide<P_F16> { using T = h8; };
+template <> struct Wide<P_SPLIT16> { using T = h8; };
 
 template <int P>
 __device__ inline void mma32(f16v& acc, const typename Wide<P>::T& a, const typename Wide<P>::T& b) {
-    if constexpr (P == P_F16) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+    if constexpr (P == P_F16 || P == P_SPLIT16) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
     else acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
 }
 
@@ -2141,6 +2165,7 @@ static hipError_t launch_transform_t(int prec, const Src& src, int blocks, hipSt
     case P_SPLIT: hipLaunchKernelGGL((transform32_kernel<P_SPLIT, Src>), dim3(blocks), dim3(256), 0, s, src); break;
     case P_BF16: hipLaunchKernelGGL((transform32_kernel<P_BF16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
     case P_F16: hipLaunchKernelGGL((transform32_kernel<P_F16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_SPLIT16: hipLaunchKernelGGL((transform32_kernel<P_SPLIT16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
     case P_FP8: hipLaunchKernelGGL((transform32_kernel<P_FP8, Src>), dim3(blocks), dim3(256), 0, s, src); break;
     default: return hipErrorInvalidValue;
     }
@@ -2174,6 +2199,7 @@ hipError_t launch_fft_transform(int prec, int log2l, const PrepSrcInline& src, i
     case P_SPLIT: return launch_fft_p<P_SPLIT>(log2l, src, blocks, s);
     case P_BF16: return launch_fft_p<P_BF16>(log2l, src, blocks, s);
     case P_F16: return launch_fft_p<P_F16>(log2l, src, blocks, s);
+    case P_SPLIT16: return launch_fft_p<P_SPLIT16>(log2l, src, blocks, s);
     case P_FP8: return launch_fft_p<P_FP8>(log2l, src, blocks, s);
     default: return hipErrorInvalidValue;
     }
@@ -2183,7 +2209,7 @@ hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipSt
 }
 
 #define CORR_CASES(X) X(P_F64, 2, 2) X(P_F64, 4, 2) X(P_F32, 4, 4) X(P_FP8, 4, 4) X(P_F32, 2, 2) X(P_FP8, 2, 2)
-#define CORR2_CASES(X) X(P_SPLIT) X(P_BF16) X(P_F16)
+#define CORR2_CASES(X) X(P_SPLIT) X(P_BF16) X(P_F16) X(P_SPLIT16)
 
 hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s) {
 #define Y(PP)                                                                                 \

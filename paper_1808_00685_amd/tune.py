@@ -31,6 +31,7 @@ CANDIDATES = {
     "bf16": [2, 3],
     "f16": [2, 3],
     "fp8_e4m3": [1, 2],
+    "split_f16": [2, 3],
 }
 M_CLASSES = [16, 64, 256]
 N_CLASSES = [512, 2048, 8192, 16384]

@@ -89,9 +89,30 @@ int main(void){
 
 def test_defaults():
     d = B.corr2d_desc_init()
-    assert d.prec == B.PREC["split_bf16"] and d.basis == 0 and d.hilbert == 0 and d.norm_mode == 0
+    assert d.prec == B.PREC["split_bf16"] and d.basis == B.BASIS["auto"] and d.hilbert == 0
+    assert d.norm_mode == 0
     assert d.in_dtype == B.DTYPE["f64"] and d.out_dtype == B.DTYPE["f32"]
     assert B.corr2d_version().startswith("corr2d")
+
+
+@pytest.mark.parametrize("prec,hilbert,expect", [
+    ("bf16", "noda", "time"), ("bf16", "circular", "time"), ("bf16", "r_compat", "fourier"),
+    ("split_bf16", "noda", "fourier"), ("split_f16", "noda", "fourier"), ("f32", "noda", "fourier"),
+    ("f64", "noda", "fourier"), ("f16", "noda", "fourier"), ("fp8_e4m3", "noda", "fourier"),
+])
+def test_auto_basis_resolution(prec, hilbert, expect):
+    """The default basis resolves to the time basis for plain BF16 (except
+    with the R bin list, which needs the Fourier basis) and to the Fourier
+    basis for every other format; plan info reports the basis in use."""
+    p = B.Plan(m=64, n1=300, n2=0, prec=prec, hilbert=hilbert)
+    assert p.info.basis == B.BASIS[expect]
+    q = B.Plan(m=64, n1=300, n2=0, prec=prec, hilbert=hilbert, basis="fourier")
+    assert q.info.basis == B.BASIS["fourier"]
+
+
+def test_split_f16_plan_scales_per_band():
+    p = B.Plan(m=256, n1=4096, n2=0, prec="split_f16")
+    assert p.info.per_band_scale == 1 and p.info.k_pad == 256 and p.info.transform == 1
 
 
 def _plan_status(**kw):
@@ -114,7 +135,9 @@ def _plan_status(**kw):
     (dict(n2=64, ld_in2=10), B.EINVAL),
     (dict(ld_out=3), B.EINVAL),
     (dict(prec=9), B.EINVAL),
-    (dict(basis=2), B.EINVAL),
+    (dict(basis=3), B.EINVAL),
+    (dict(prec=7), B.EINVAL),
+    (dict(prec="split_f16", flags=B.FLAG_NO_PER_BAND_SCALE), B.EUNSUPPORTED),
     (dict(hilbert=5), B.EINVAL),
     (dict(norm_mode=7), B.EINVAL),
     (dict(out_layout=3), B.EINVAL),
@@ -386,3 +409,4 @@ def test_result_object_argument_errors_before_any_call():
         B.corr2d(y, y, layout="upper_aligned")
     with pytest.raises(ValueError):
         B.hetero(y, torch.zeros(9, 10, dtype=torch.float64))
+

@@ -19,7 +19,7 @@ from .gpu_helpers import (ELEMENT_TAU, TOL, check_homo_structure, packed_index, 
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"]
+PRECS = ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3", "split_f16"]
 
 
 def _t(a, dev, dtype=None):
@@ -71,7 +71,7 @@ def test_small_workload_f64(gpu):
     assert np.abs(np.diag(phi) - np.var(S, axis=0, ddof=1)).max() <= 1e-12 * np.abs(phi).max()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "split_f16"])
 @pytest.mark.parametrize("basis", ["fourier", "time"])
 @pytest.mark.parametrize("hilbert", ["noda", "circular"])
 def test_modes(gpu, prec, basis, hilbert):
@@ -230,7 +230,7 @@ def test_batched_upper_aligned(gpu, prec):
         assert np.all(np.diag(Q) == 0)
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
+@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16", "split_f16"])
 @pytest.mark.parametrize("tile", [2, 3])
 @pytest.mark.parametrize("layout", ["full", "upper_packed", "upper_aligned"])
 def test_lds_staged_tile_shapes(gpu, prec, tile, layout):
@@ -304,7 +304,7 @@ def test_hetero_parity(gpu, prec, m, n1, n2):
     assert rel_fro(_np(psi), psi_o) <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "f32", "bf16", "f64", "f16", "fp8_e4m3"])
+@pytest.mark.parametrize("prec", ["split_bf16", "f32", "bf16", "f64", "f16", "fp8_e4m3", "split_f16"])
 @pytest.mark.parametrize("m,n1,n2", [(256, 640, 0), (181, 500, 0), (128, 400, 300)])
 def test_error_within_elementwise_bound(gpu, prec, m, n1, n2):
     """Every entry lies within its own bound, whatever its cancellation:
@@ -338,7 +338,7 @@ def test_error_within_elementwise_bound(gpu, prec, m, n1, n2):
         assert np.median(np.abs(phi_o) / bound_phi) > (10.0 if tau <= 2.0 ** -9 else 1.5)
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
+@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16", "split_f16"])
 def test_hetero_direct_and_staged_stores_agree(gpu, prec):
     """Interior tiles of a heterocorrelation are stored straight from the
     accumulators when every output row is whole 128-byte lines (row stride
@@ -680,7 +680,7 @@ def test_interpolation_hetero_f32_input_scaled(gpu):
 # --------------------------------------------------------------------------
 # Radix FFT transform (power-of-two 128 <= m <= 1024, Fourier basis)
 # --------------------------------------------------------------------------
-FFT_PRECS = ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3"]
+FFT_PRECS = ["f64", "f32", "split_bf16", "bf16", "f16", "fp8_e4m3", "split_f16"]
 
 
 def _transform(plan):
