@@ -181,14 +181,14 @@ LAYOUT_TEXT = {"upper_aligned": "rows aligned to 128 bytes",
 
 
 def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, ref,
-                layout="upper_packed", alpha=0.0):
+                layout="upper_packed", alpha=0.0, flags=0):
     """Time `steps` calls; returns a dict of measurements for this form, with
     its error against the oracle over the full matrices.  ref = (oracle Phi,
     oracle Psi, diagonal positions, aligned-layout gather index), the oracle's
     values packed as upper triangles on the GPU."""
     out_dtype = "f64" if prec == "f64" else "f32"
     plan = B.Plan(m=m, n1=n, n2=0, prec=prec, basis=basis, out_layout=layout,
-                  in_dtype="f64", out_dtype=out_dtype, scale_alpha=alpha)
+                  in_dtype="f64", out_dtype=out_dtype, scale_alpha=alpha, flags=flags)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     numel = B.out_elements(layout, n)
     phi = torch.empty(numel, dtype=tdt, device=y.device)
@@ -219,7 +219,11 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, ref,
     entries = n * (n + 1) // 2
     alg_flops = 4.0 * m * entries
     executed = 2.0 * 2.0 * info.tiles * info.tile_m * info.tile_n * info.k_pad
-    if prec in ("split_bf16", "split_f16"):
+    sel = B.selection(ws, plan)
+    if sel is not None:
+        # hi*hi over every K block, hi*lo and lo*hi over the selected ones
+        executed *= 1 + 2 * sel[0] / len(sel[1])
+    elif prec in ("split_bf16", "split_f16"):
         executed *= 3
     kernel_ms = float(np.mean(kms))
     esz = 8 if out_dtype == "f64" else 4
@@ -240,6 +244,7 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, ref,
         "err_phi": err_phi,
         "err_psi": err_psi,
         "tile": f"{info.tile_m}x{info.tile_n}",
+        "row_select": None if sel is None else {"split_k_blocks": sel[0], "k_blocks": len(sel[1])},
         "alg_flops": alg_flops, "executed_flops": executed, "kernel_bytes": kernel_bytes,
     }
     del phi, psi, ws, plan
@@ -611,6 +616,11 @@ def main():
                             ("bf16", "time"), ("f64", "fourier")):
             variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, ref,
                                         layout=layout))
+        # the row-selective split (low plane on the high-energy Fourier rows
+        # only; target 1e-5)
+        for prec in ("split_bf16", "split_f16"):
+            variants.append(run_variant(B, torch, y, n, m, prec, "fourier", vs, 1, ev, ref,
+                                        layout=layout, flags=B.FLAG_SPLIT_ROWS))
         # Pareto scaling (alpha = 0.5) of the headline form: the oracle's
         # values times its scaling factors (oracle.corr2d's alpha)
         f = torch.as_tensor(oracle.scaling_factors(oracle.band_sd(oracle.dynamic(S)[0]), 0.5),

@@ -138,6 +138,19 @@ typedef enum corr2d_dtype { CORR2D_DTYPE_F64 = 0, CORR2D_DTYPE_F32 = 1 } corr2d_
 #define CORR2D_FLAG_NO_PER_BAND_SCALE 0x2u /* force scaling off (F16 only)          */
 #define CORR2D_FLAG_SEQUENTIAL 0x4u      /* batched: one launch chain per data set */
 #define CORR2D_FLAG_NO_GRAPH 0x8u        /* batched: launch directly, no hipGraph  */
+/* Row-selective split (split formats, Fourier basis, m <= 1024, single and
+ * heterocorrelation plans): the low plane enters only the products of the
+ * packed Fourier rows that carry most of the energy (Eq. (symmeFT): a band
+ * spectrum's dynamic spectra concentrate in the low frequencies).  Each
+ * call measures the energy of every row of its operands, ranks the pairs
+ * of 16-row K blocks by the energy of their hi*hi rounding errors, and
+ * keeps the low plane for the fewest leading pairs whose complement holds
+ * at most the fraction of that energy which the target desc.split_tol
+ * allows (the modelled relative error of Phi from the rows left to hi*hi
+ * is a quarter of the target).  The target bounds Phi's modelled error; Psi
+ * follows it unless Psi itself cancels strongly.  The selection is written
+ * to the workspace (plan info sel_offset).                                 */
+#define CORR2D_FLAG_SPLIT_ROWS 0x20u
 #define CORR2D_FLAG_TRANSFORM_MATMUL 0x10u /* perturbation-axis transform as the MFMA
                                            product with the table also where the
                                            radix FFT applies (power-of-two
@@ -182,6 +195,8 @@ typedef struct corr2d_desc {
     int64_t m_in;
     int32_t interp;     /* corr2d_interp                                          */
     int32_t reserved2;
+    double split_tol;   /* CORR2D_FLAG_SPLIT_ROWS: target relative error of the
+                           result (finite, >= 0; 0 = 1e-5)                      */
 } corr2d_desc;
 
 /* Interpolation of Sec. 4.1: piecewise linear (R's approxfun), or the cubic
@@ -232,6 +247,11 @@ typedef struct corr2d_plan_info {
      * ref1_offset.  Batched plans: 0 (not reported).                         */
     size_t ref1_offset;
     size_t ref2_offset;
+    /* CORR2D_FLAG_SPLIT_ROWS: byte offset in the workspace of the selection
+     * record a call writes (readable once the call has completed): int32
+     * count of the K blocks of 16 packed rows that carried the low plane,
+     * then the order of the k_pad/16 K blocks, those first.  0 otherwise.  */
+    size_t sel_offset;
 } corr2d_plan_info;
 
 /* Fill *d with defaults: FP64 input, FP32 output, SPLIT_BF16, AUTO basis, NODA

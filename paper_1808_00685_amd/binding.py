@@ -29,6 +29,7 @@ FLAG_NO_PER_BAND_SCALE = 0x2
 FLAG_SEQUENTIAL = 0x4
 FLAG_NO_GRAPH = 0x8
 FLAG_TRANSFORM_MATMUL = 0x10
+FLAG_SPLIT_ROWS = 0x20
 
 EXPORTED = [
     "corr2d_desc_init", "corr2d_plan", "corr2d_batched_plan", "corr2d_plan_destroy",
@@ -49,6 +50,7 @@ class corr2d_desc(ctypes.Structure):
         ("scale_alpha", ctypes.c_double),
         ("t_in", ctypes.POINTER(ctypes.c_double)), ("m_in", ctypes.c_int64),
         ("interp", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+        ("split_tol", ctypes.c_double),
     ]
 
 
@@ -65,6 +67,7 @@ class corr2d_plan_info(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t), ("items", ctypes.c_int64),
         ("out_elements", ctypes.c_int64), ("transform", ctypes.c_int32), ("basis", ctypes.c_int32),
         ("ref1_offset", ctypes.c_size_t), ("ref2_offset", ctypes.c_size_t),
+        ("sel_offset", ctypes.c_size_t),
     ]
 
 
@@ -305,7 +308,7 @@ def out_elements(layout, n1, n2=0):
 
 def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="auto",
          hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0,
-         t_in=None, interp="none", m_out=None, stream=None):
+         t_in=None, interp="none", m_out=None, stream=None, split_tol=0.0):
     """Homocorrelation of y (torch, m x n, float64/float32, on the GPU).  With
     interp "linear" or "spline", y's rows were taken at perturbation values
     t_in and are resampled on m_out (default: as many) equidistant values."""
@@ -319,7 +322,7 @@ def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="a
                 in_dtype="f64" if y.dtype == torch.float64 else "f32",
                 out_dtype=out_dtype, prec=prec, basis=basis, hilbert=hilbert, norm_mode=norm,
                 norm_value=norm_value, out_layout=layout, flags=flags, tile=tile,
-                scale_alpha=alpha, t_in=t_in, interp=interp)
+                scale_alpha=alpha, t_in=t_in, interp=interp, split_tol=split_tol)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     numel = out_elements(layout, n)
     phi = torch.empty(numel, dtype=tdt, device=y.device)
@@ -333,7 +336,7 @@ def homo(y, ref=None, prec="split_bf16", out_dtype=None, layout="full", basis="a
 
 def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basis="auto",
            hilbert="noda", norm="noda", norm_value=0.0, flags=0, tile=0, alpha=0.0,
-           t_in=None, interp="none", m_out=None, stream=None):
+           t_in=None, interp="none", m_out=None, stream=None, split_tol=0.0):
     """Heterocorrelation of y1 (m x n1) with y2 (m x n2), both on the GPU;
     interp, t_in, m_out as for homo()."""
     import torch
@@ -349,13 +352,26 @@ def hetero(y1, y2, ref1=None, ref2=None, prec="split_bf16", out_dtype=None, basi
                 in_dtype="f64" if y1.dtype == torch.float64 else "f32",
                 out_dtype=out_dtype, prec=prec, basis=basis, hilbert=hilbert, norm_mode=norm,
                 norm_value=norm_value, out_layout="full", flags=flags, tile=tile,
-                scale_alpha=alpha, t_in=t_in, interp=interp)
+                scale_alpha=alpha, t_in=t_in, interp=interp, split_tol=split_tol)
     tdt = torch.float64 if out_dtype == "f64" else torch.float32
     phi = torch.empty(n1, n2, dtype=tdt, device=y1.device)
     psi = torch.empty(n1, n2, dtype=tdt, device=y1.device)
     ws = plan.workspace(y1.device)
     corr2d_hetero(plan.handle, y1, ref1, y2, ref2, phi, psi, ws, stream=stream)
     return phi, psi, plan, ws
+
+
+def selection(ws, plan):
+    """The row selection a completed row-selective call left in its
+    workspace: (K blocks that carried the low plane, the K-block order), read
+    back to the host (int32 record at plan info sel_offset)."""
+    info = plan.info if hasattr(plan, "info") else corr2d_plan_get_info(plan)
+    if not info.sel_offset:
+        return None
+    import torch
+    nkb = info.k_pad // 16
+    rec = ws[info.sel_offset:info.sel_offset + 4 * (1 + nkb)].view(torch.int32).cpu().tolist()
+    return rec[0], rec[1:]
 
 
 def workspace_vector(ws, offset, n):

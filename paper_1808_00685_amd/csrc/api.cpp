@@ -131,6 +131,11 @@ struct corr2d_plan_s {
     // single / hetero
     Geo g1, g2;
     bool fft = false;         // radix FFT transform (else the table product)
+    // row-selective split: energy partials per operand, the selection record
+    bool rowsel = false;
+    double fmax = 0.0;
+    size_t energy_off[3] = {0, 0, 0};
+    size_t sel_off = 0;
     size_t table_off = 0;
     SetLayout s1, s2;
     size_t ws_bytes = 0;
@@ -217,7 +222,14 @@ corr2d_status check_common(const corr2d_desc* d) {
                 return fail(CORR2D_EINVAL, "t_in must be strictly increasing (t_in[%lld])", (long long)i);
         }
     }
-    if (d->flags & ~0x1fu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
+    if (d->flags & ~0x3fu) return fail(CORR2D_EINVAL, "unknown flag bits 0x%x", d->flags);
+    if (!std::isfinite(d->split_tol) || d->split_tol < 0.0)
+        return fail(CORR2D_EINVAL, "split_tol must be finite and >= 0");
+    if ((d->flags & CORR2D_FLAG_SPLIT_ROWS) && d->prec != CORR2D_PREC_SPLIT_BF16 &&
+        d->prec != CORR2D_PREC_SPLIT_F16)
+        return fail(CORR2D_EUNSUPPORTED, "the row-selective split needs a split format");
+    if ((d->flags & CORR2D_FLAG_SPLIT_ROWS) && d->basis == CORR2D_BASIS_TIME)
+        return fail(CORR2D_EUNSUPPORTED, "the row-selective split works on the Fourier rows");
     if (d->prec == CORR2D_PREC_FP8_E4M3 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
         return fail(CORR2D_EUNSUPPORTED, "FP8 e4m3 requires per-band scaling (range 448)");
     if (d->prec == CORR2D_PREC_SPLIT_F16 && (d->flags & CORR2D_FLAG_NO_PER_BAND_SCALE))
@@ -420,6 +432,45 @@ hipError_t launch_prep_tables(const corr2d_plan_s* p, const TableSrcInline& ts, 
 // tile I pairs with column tiles J >= R I of the R T column tiles.
 int64_t triangle_tiles(int64_t T, int64_t R) { return R * T * (T + 1) / 2; }
 
+// Fraction of the hi*hi rounding-error energy the rows without the low
+// plane may hold: with RNE halves of unit roundoff u (2^-8 BF16, 2^-11
+// FP16) the rounding errors are about uniform, rms u/sqrt(3); the error
+// energy of the products left to hi*hi, 2 (u/sqrt(3))^2 times their share
+// f of sum_k E_k^2, over ||Phi||_F^2 >= sum_k E_k^2 (the diagonal of the
+// rows' Gram matrix) gives a relative error of (u/sqrt(3)) sqrt(2 f); it is
+// held to a quarter of the target eps (the kept products, the transform and
+// the FP32 accumulation take the rest):  f = (eps / (4 u / sqrt(3)))^2 / 2.
+double split_fmax(const corr2d_desc* d) {
+    const double eps = d->split_tol > 0.0 ? d->split_tol : 1e-5;
+    const double u = d->prec == CORR2D_PREC_SPLIT_F16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
+    const double r = eps / (4.0 * u / std::sqrt(3.0));
+    return 0.5 * r * r;
+}
+
+// Energy and selection launches of a row-selective call: operand 0 the
+// left A (set 1), 1 the right A (set 2; none for a homocorrelation), 2 the
+// right B.
+hipError_t launch_selection(const corr2d_plan_s* p, void* ws, hipStream_t s) {
+    SelJob J{};
+    const SetLayout& r = p->hetero ? p->s2 : p->s1;
+    const Geo& gr = p->hetero ? p->g2 : p->g1;
+    J.X[0] = at<char>(ws, p->s1.A0);
+    J.X[1] = p->hetero ? at<char>(ws, p->s2.A0) : J.X[0];
+    J.X[2] = at<char>(ws, r.B0);
+    J.s[0] = p->scale ? at<float>(ws, p->s1.sA) : nullptr;
+    J.s[1] = p->scale ? at<float>(ws, p->hetero ? p->s2.sA : p->s1.sA) : nullptr;
+    J.s[2] = p->scale ? at<float>(ws, r.sB) : nullptr;
+    for (int o = 0; o < 3; ++o) J.part[o] = at<float>(ws, p->energy_off[o]);
+    J.panels[0] = (int32_t)(p->g1.n_pad / 128);
+    J.panels[1] = p->hetero ? (int32_t)(p->g2.n_pad / 128) : 0;
+    J.panels[2] = (int32_t)(gr.n_pad / 128);
+    J.kp = p->g1.kp;
+    J.prec = p->d.prec;
+    J.fmax = p->fmax;
+    J.sel = at<int32_t>(ws, p->sel_off);
+    return launch_row_select(J, s);
+}
+
 CorrJob make_corr_job(const corr2d_plan_s* p, const Geo& g1, const SetLayout& s1, const Geo& g2,
                       const SetLayout& s2, void* ws, void* phi, void* psi, bool homo, double c,
                       const Tile& tile, int64_t ld_out, int layout) {
@@ -560,6 +611,27 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
         p->s2 = layout_set(p->g2, d->prec, t64, true, !p->fft, &off);
         p->ntiles = (p->g1.n_pad / (32 * p->tile.fm)) * (p->g2.n_pad / (32 * p->tile.fn));
     }
+    if (d->flags & CORR2D_FLAG_SPLIT_ROWS) {
+        if (p->d.basis != CORR2D_BASIS_FOURIER) {
+            delete p;
+            return fail(CORR2D_EUNSUPPORTED, "the row-selective split works on the Fourier rows");
+        }
+        if (p->g1.kp > 16 * kMaxSelBlocks) {
+            delete p;
+            return fail(CORR2D_EUNSUPPORTED, "the row-selective split orders at most %d K blocks (m <= %d)",
+                        kMaxSelBlocks, 16 * kMaxSelBlocks);
+        }
+        p->rowsel = true;
+        p->fmax = split_fmax(&p->d);
+        const int64_t np0 = p->g1.n_pad / 128, np2 = (hetero ? p->g2.n_pad : p->g1.n_pad) / 128;
+        const int64_t np[3] = {np0, hetero ? np2 : 0, np2};
+        for (int o = 0; o < 3; ++o) {
+            p->energy_off[o] = off;
+            off = align256(off + (size_t)std::max<int64_t>(np[o], 1) * p->g1.kp * sizeof(float));
+        }
+        p->sel_off = off;
+        off = align256(off + (1 + kMaxSelBlocks) * sizeof(int32_t));
+    }
     if (d->interp != CORR2D_INTERP_NONE) {
         // weights of the resampling (FP64, host), uploaded with every call;
         // the resampled spectra live in the workspace
@@ -583,11 +655,11 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     if (log_enabled())
         std::fprintf(stderr,
                      "corr2d: plan %s m=%lld n1=%lld n2=%lld layout=%d tile=%d (%dx%d) tiles=%lld "
-                     "transform=%s prep_launches=%d per_band_scale=%d workspace=%zu B tune: %s\n",
+                     "transform=%s prep_launches=%d per_band_scale=%d row_select=%d workspace=%zu B tune: %s\n",
                      prec_name(d->prec), (long long)d->m, (long long)d->n1, (long long)d->n2, d->out_layout,
                      p->tile.id, 32 * p->tile.fm, 32 * p->tile.fn, (long long)p->ntiles,
                      p->fft ? "radix FFT" : "DFT table product", p->fft ? 2 : (merged_prep(p) ? 2 : (needs_qn(p) ? 4 : 3)),
-                     (int)p->scale, p->ws_bytes, tune_source());
+                     (int)p->scale, (int)p->rowsel, p->ws_bytes, tune_source());
     *out = p;
     return ok();
 }
@@ -601,6 +673,8 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
     if (st != CORR2D_OK) return st;
     if (common->interp != CORR2D_INTERP_NONE)
         return fail(CORR2D_EUNSUPPORTED, "interpolation is not available for batched plans");
+    if (common->flags & CORR2D_FLAG_SPLIT_ROWS)
+        return fail(CORR2D_EUNSUPPORTED, "the row-selective split is not available for batched plans");
     for (int64_t i = 0; i < count; ++i) {
         const corr2d_item& it = items[i];
         if (it.m < 2 || it.m > kMaxM) return fail(CORR2D_EINVAL, "item %lld: m = %lld out of range", (long long)i, (long long)it.m);
@@ -747,6 +821,7 @@ corr2d_status corr2d_plan_get_info(corr2d_plan_t p, corr2d_plan_info* info) {
         info->c = p->c;
         info->transform = p->fft ? 1 : 0;
         info->basis = p->d.basis;
+        info->sel_offset = p->rowsel ? p->sel_off : 0;
         info->ref1_offset = p->s1.ref;
         info->ref2_offset = p->hetero ? p->s2.ref : p->s1.ref;
     }
@@ -846,9 +921,11 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
         e = launch_transform(p->d.prec, ps, ps.blocks0, s);
     }
     if (e != hipSuccess) return device_fail(e, "transform launch");
+    if (p->rowsel && (e = launch_selection(p, ws, s)) != hipSuccess) return device_fail(e, "row selection launch");
 
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g1, p->s1, ws, phi, psi, true, p->c, p->tile,
                               p->d.ld_out, p->d.out_layout);
+    if (p->rowsel) C.kb_sel = at<int32_t>(ws, p->sel_off);
     if (g_ev_before) hipEventRecord(g_ev_before, s);
     e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
     if (e != hipSuccess) return device_fail(e, "correlation launch");
@@ -910,9 +987,11 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
         e = launch_transform(p->d.prec, ps, ps.blocks0 + transform_blocks(p->g2, p->d.prec), s);
     }
     if (e != hipSuccess) return device_fail(e, "transform launch");
+    if (p->rowsel && (e = launch_selection(p, ws, s)) != hipSuccess) return device_fail(e, "row selection launch");
 
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g2, p->s2, ws, phi, psi, false, p->c, p->tile,
                               p->d.ld_out, CORR2D_LAYOUT_FULL);
+    if (p->rowsel) C.kb_sel = at<int32_t>(ws, p->sel_off);
     if (g_ev_before) hipEventRecord(g_ev_before, s);
     e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
     if (e != hipSuccess) return device_fail(e, "correlation launch");

@@ -109,6 +109,26 @@ struct InterpJob {
 // the outputs fit the 256 MB memory-side cache, and 10-23 % slower beyond.
 constexpr int64_t kNearStoreBytes = int64_t(192) << 20;
 
+// Row selection of the split formats (Fourier basis): the energy of every
+// packed Fourier row k of each operand, E_X[k] = sum_nu (X[k][nu] / s_nu)^2
+// from the high plane, then the K-block order of the contraction.  Operands:
+// 0 the left A, 1 the right A, 2 the right B (a homocorrelation gives
+// operand 1 no panels: its right A is operand 0).  Row pairs of K blocks (32 rows) are ranked by
+// sum_k E_0[k] (E_1[k] + E_2[k]), the energy of the hi*hi rounding errors of
+// their products, and the fewest leading pairs whose complement holds at
+// most fmax of that energy keep the low plane.
+constexpr int kMaxSelBlocks = 64;   // K blocks a selection orders (kp <= 1024)
+struct SelJob {
+    const void* X[3];      // high planes (panel-blocked)
+    const float* s[3];     // per-band scales (nullptr: unscaled)
+    float* part[3];        // per-panel row energies: panels_o x kp floats each
+    int32_t panels[3];     // column panels of 128 per operand
+    int32_t kp;
+    int32_t prec;
+    double fmax;           // fraction of the error energy left to hi*hi
+    int32_t* sel;          // [0] split K blocks, then the kp/16 K-block order
+};
+
 struct CorrJob {
     const void* L0; const void* L1;   // left operand planes (set 1, A)
     const void* RA0; const void* RA1; // right synchronous operand (set 2, A)
@@ -129,6 +149,11 @@ struct CorrJob {
                         // kNearStoreBytes): direct stores at system scope
     int64_t ntiles;
     double c;           // FP64 normalization of the contraction
+    // Row-selective split (split formats, nullptr otherwise): [0] the number
+    // of K blocks (an even count, leading the order) that carry the low
+    // plane, then the order of the kp/16 K blocks (at most 64), written by
+    // the selection kernel of the same call.
+    const int32_t* kb_sel;
 };
 
 }  // namespace corr2d

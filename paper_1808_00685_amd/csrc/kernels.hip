@@ -1736,18 +1736,6 @@ template <int P, int TM> constexpr int corr2_lds_bytes() {
 }
 
 
-// Wait until at most `ahead` stages of OPSW loads each are outstanding
-// (vector memory operations of one wave complete in issue order).
-template <int OPSW, int MAXA>
-__device__ inline void wait_stages(int ahead) {
-    if constexpr (MAXA == 0) {
-        wait_vmcnt<0>();
-    } else {
-        if (ahead >= MAXA) wait_vmcnt<OPSW * MAXA>();
-        else wait_stages<OPSW, MAXA - 1>(ahead);
-    }
-}
-
 // Epilogue of one TM x 128 output tile of the LDS-staged kernel.  The waves
 // scale their accumulators in FP64 by the column factor, round once to FP32
 // and write them into an LDS tile (the operand ring is free by then), then
@@ -1831,11 +1819,39 @@ __device__ inline void stage_out(const CorrJob& C, int I, int J, f16v (&acc)[2][
     store_tile<TM, kTileN2, threads2(TM), float>(C, i0, j0, T, sexp, psi, tid);
 }
 
+// Fragments of one K stage held in registers: NP planes (both halves of a
+// split format, or the high plane alone) of the left rows and the two right
+// operands, for the wave's two 32-row blocks.
+template <class FT, int NP>
+struct StageFrags {
+    FT la[NP][2], ra[NP][2], rb[NP][2];
+};
+
+// Wait until at most u * CPW vector memory operations of this wave are
+// outstanding (u <= MAXU; the encoding needs an immediate, so the runtime
+// count selects the immediate for it).
+template <int CPW, int MAXU>
+__device__ inline void wait_units(int u) {
+    if constexpr (MAXU == 0) {
+        wait_vmcnt<0>();
+    } else {
+        if (u >= MAXU) wait_vmcnt<CPW * MAXU>();
+        else wait_units<CPW, MAXU - 1>(u);
+    }
+}
+
 // One TM x 128 output tile: the K loop over a ring of LDS stages filled by
 // direct-to-LDS loads, then the epilogue.  A plane's stage is CH = TM/32 + 8
 // chunks of 1 KB: chunks 0..TM/32-1 hold the left panels, then 4 for the
 // synchronous right panel and 4 for the asynchronous one; wave w copies
 // chunks w, w + NW, ... of every plane.
+//
+// Row-selective split (C.kb_sel set, split formats only): the K blocks run
+// in the order the list gives, and only the first nsel of them (the
+// highest-energy Fourier rows, in pairs of blocks) carry the low plane; the
+// others are copied and multiplied with the high plane alone (hi*hi).  A
+// stage then holds one or two planes, and the waits count the copies of
+// the stages actually in flight.
 template <int P, int TM>
 __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int* sexp) {
     using FT = typename Wide<P>::T;
@@ -1846,7 +1862,7 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
     constexpr int CH = TM / 32 + 8;      // 1 KB chunks per plane and stage
     constexpr int CPW = CH / NW;         // chunks per wave and plane
     constexpr int PB = TM * 32 + 8192;   // plane bytes per stage
-    constexpr int OPSW = CPW * PL;       // loads per wave per stage
+    constexpr int MAXU = PL * (S - 1);   // plane-stages a wave can have in flight
     // opaque copy of the thread index: in a persistent tile loop the values
     // derived from it are then recomputed per tile rather than kept live
     // (and spilled) across the epilogue
@@ -1856,6 +1872,15 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
     const int wi = w >> 1, wj = w & 1;
     const int nkb = C.kp >> 4;
     const int64_t panel_bytes = (int64_t)nkb * 4096;
+    // K-block order and split count: lane l holds the l-th block of the
+    // order (nkb <= 64 where a list is given); nsel blocks carry both planes
+    // (clamped, so that a damaged list cannot send a copy out of range)
+    const bool listed = PL == 2 && C.kb_sel != nullptr;
+    const int nsel = PL == 1 ? 0
+                     : (listed ? min(max(__builtin_amdgcn_readfirstlane(C.kb_sel[0]), 0), nkb) & ~1 : nkb);
+    const int order = listed && lane < nkb ? min(max(C.kb_sel[1 + lane], 0), nkb - 1) : lane;
+    auto block_of = [&](int kb) { return listed ? __builtin_amdgcn_readlane(order, kb) : kb; };
+    auto planes_of = [&](int kb) { return kb < nsel ? PL : 1; };
 
     const char* src[PL][CPW];
 #pragma unroll
@@ -1872,14 +1897,26 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
             }
             src[p][k] = b + (c & 3) * 1024 + lane * 16;
         }
+    // copy stage kb (its block of the order) with its planes
     auto issue = [&](int kb) {
         char* dst = lds + (kb % S) * SB;
+        const int64_t off = (int64_t)block_of(kb) * 4096;
+        const int np = planes_of(kb);
 #pragma unroll
         for (int p = 0; p < PL; ++p)
+            if (p < np)
 #pragma unroll
-            for (int k = 0; k < CPW; ++k)
-                __builtin_amdgcn_global_load_lds(AS_GLOBAL(src[p][k] + kb * 4096),
-                                                 AS_LDS(dst + p * PB + (w + k * NW) * 1024), 16, 0, 0);
+                for (int k = 0; k < CPW; ++k)
+                    __builtin_amdgcn_global_load_lds(AS_GLOBAL(src[p][k] + off),
+                                                     AS_LDS(dst + p * PB + (w + k * NW) * 1024), 16, 0, 0);
+    };
+    // plane-stages of stages lo..hi (inclusive, clipped to the K range): a
+    // wave issues CPW copies for each
+    auto units = [&](int lo, int hi) {
+        hi = min(hi, nkb - 1);
+        if (hi < lo) return 0;
+        const int sel = max(0, min(hi, nsel - 1) - lo + 1);
+        return (hi - lo + 1) + (PL - 1) * sel;
     };
 
     // LDS byte offsets of this lane's fragment rows (K-block half g = lane/32)
@@ -1903,14 +1940,15 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
         }
 
     // Fragments of one stage, held in registers: the K loop reads stage kb+1
-    // from LDS while the MFMAs of stage kb run (two register sets).
-    struct Frags {
-        FT la[PL][2], ra[PL][2], rb[PL][2];
-    };
-    auto load_frags = [&](Frags& F, int kb) {
+    // from LDS while the MFMAs of stage kb run (two register sets).  NP
+    // planes: the split stages' fragments hold both, the others the high
+    // plane only (separate register sets, so that no stale low-plane
+    // fragment stays live through the single-plane stages).
+    auto load_frags = [&](auto& F, int kb) {
+        constexpr int NP = sizeof(F.la) / sizeof(F.la[0]);
         const char* st = lds + (kb % S) * SB;
 #pragma unroll
-        for (int p = 0; p < PL; ++p)
+        for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 F.la[p][a] = *(const FT*)(st + p * PB + offA[a]);
@@ -1919,12 +1957,13 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
             }
     };
     // MFMAs of one stage for the 32-row block a of the wave's 64 rows
-    auto mfma_rows = [&](const Frags& F, int a) {
+    auto mfma_rows = [&](const auto& F, int a) {
+        constexpr int NP = sizeof(F.la) / sizeof(F.la[0]);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             mma32<P>(ap[a][b], F.la[0][a], F.ra[0][b]);
             mma32<P>(aq[a][b], F.la[0][a], F.rb[0][b]);
-            if constexpr (PL == 2) {
+            if constexpr (NP == 2) {
                 mma32<P>(ap[a][b], F.la[0][a], F.ra[1][b]);
                 mma32<P>(aq[a][b], F.la[0][a], F.rb[1][b]);
                 mma32<P>(ap[a][b], F.la[1][a], F.ra[0][b]);
@@ -1940,9 +1979,12 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
     // Each wave finishes its own fragment reads of stage kb (lgkmcnt) before
     // the barrier, so after it the slot of stage kb is free and the copy of
     // stage kb + S goes there: every slot of the ring holds a stage in
-    // flight or being read, and a copy has S - 1 steps to land.
-    auto step = [&](Frags& Fc, Frags& Fn, int kb) {
-        wait_stages<OPSW, S - 2>(min(S - 2, nkb - 2 - kb));
+    // flight or being read, and a copy has S - 1 steps to land.  Before the
+    // barrier, stage kb+1 must have landed: the copies of stages kb+2 ..
+    // kb+S-1 may still be in flight (a wave's vector memory operations
+    // complete in issue order).
+    auto step = [&](const auto& Fc, auto& Fn, int kb) {
+        wait_units<CPW, MAXU>(units(kb + 2, kb + S - 1));
         wait_lgkm0();
         lds_barrier();
         if (kb + S < nkb) issue(kb + S);
@@ -1952,31 +1994,59 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
         __builtin_amdgcn_sched_barrier(0);
         mfma_rows(Fc, 1);
     };
+    // the last stage: the scales' exponents are loaded meanwhile (every copy
+    // has landed, so these loads are the only ones in flight and the last
+    // stage's MFMAs hide them)
+    ScaleExps<TM, kTileN2, threads2(TM)> se;
+    auto last = [&](const auto& F) {
+        se.load(C, (int64_t)I * TM, (int64_t)J * kTileN2, tid);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_rows(F, 0);
+        mfma_rows(F, 1);
+        __builtin_amdgcn_sched_barrier(0);
+    };
 
     lds_barrier();   // the ring is free (previous tile of a persistent loop)
 #pragma unroll
     for (int st = 0; st < S; ++st)
         if (st < nkb) issue(st);
-    wait_stages<OPSW, S - 1>(min(S - 1, nkb - 1));
+    wait_units<CPW, MAXU>(units(1, S - 1));
     lds_barrier();
-    Frags F0, F1;
-    load_frags(F0, 0);
-    // nkb is even and at least 2: pairs of steps, then the last pair, whose
-    // second stage needs no further load (every load has landed and is
-    // visible after the last step's barrier)
-    for (int kb = 0; kb + 2 < nkb; kb += 2) {
-        step(F0, F1, kb);
-        step(F1, F0, kb + 1);
+    // nkb and nsel are even and nkb is at least 2: pairs of steps, then the
+    // last pair, whose second stage needs no further load (every load has
+    // landed and is visible after the last step's barrier)
+    if (PL == 1 || nsel == nkb) {
+        // every stage with all the format's planes
+        StageFrags<FT, PL> F0, F1;
+        load_frags(F0, 0);
+        for (int kb = 0; kb + 2 < nkb; kb += 2) {
+            step(F0, F1, kb);
+            step(F1, F0, kb + 1);
+        }
+        step(F0, F1, nkb - 2);
+        last(F1);
+    } else if constexpr (PL == 2) {
+        // row-selective: the split stages first, then the high plane alone
+        StageFrags<FT, 1> G0, G1;
+        if (nsel > 0) {
+            StageFrags<FT, 2> F0, F1;
+            load_frags(F0, 0);
+            for (int kb = 0; kb + 2 < nsel; kb += 2) {
+                step(F0, F1, kb);
+                step(F1, F0, kb + 1);
+            }
+            step(F0, F1, nsel - 2);
+            step(F1, G0, nsel - 1);
+        } else {
+            load_frags(G0, 0);
+        }
+        for (int kb = nsel; kb + 2 < nkb; kb += 2) {
+            step(G0, G1, kb);
+            step(G1, G0, kb + 1);
+        }
+        step(G0, G1, nkb - 2);
+        last(G1);
     }
-    step(F0, F1, nkb - 2);
-    // the scales' exponents: every copy has landed, so these loads are the
-    // only ones in flight and the last stage's MFMAs hide them
-    ScaleExps<TM, kTileN2, threads2(TM)> se;
-    se.load(C, (int64_t)I * TM, (int64_t)J * kTileN2, tid);
-    __builtin_amdgcn_sched_barrier(0);
-    mfma_rows(F1, 0);
-    mfma_rows(F1, 1);
-    __builtin_amdgcn_sched_barrier(0);
     se.store(sexp, tid);
 
     // epilogue through LDS, one output at a time
@@ -2070,6 +2140,118 @@ __global__ __launch_bounds__(256, FM * FN < 16 ? 2 : 1) void corr_persistent_ker
         decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
         corr_tile<P, FM, FN>(C, I, J, corr_lds, sexp);
     }
+}
+
+// =========================================================================
+// Row selection of the split formats
+// =========================================================================
+// Energy of every packed Fourier row of one operand over one panel of 128
+// spectral points (workgroups in turn over the panels of operands 0, 1, 2;
+// operand 1 has none for a homocorrelation, whose right A is its left A):
+// thread t reads its point's 16 values of each K block
+// (32 bytes, the halves swapped as the panel-blocked layout stores them),
+// unscaled, and the workgroup sums their squares per row through LDS.
+template <int P>
+__global__ __launch_bounds__(128) void row_energy_kernel(SelJob J) {
+    __shared__ float sq[128][17];
+    __shared__ float part[8][16];
+    int b = blockIdx.x, o = 0;
+    while (o < 2 && b >= J.panels[o]) b -= J.panels[o++];
+    const int t = threadIdx.x;
+    const int nkb = J.kp >> 4;
+    const int64_t i = (int64_t)b * 128 + t;   // spectral point
+    const float inv = J.s[o] ? 1.0f / J.s[o][i] : 1.0f;   // power of two: exact
+    const uint16_t* X = (const uint16_t*)J.X[o];
+    const int swz = row_swizzle(i);
+    for (int kb = 0; kb < nkb; ++kb) {
+        const uint4* src = (const uint4*)(X + (((int64_t)b * nkb + kb) * 128 + t) * 16);
+        const uint4 h[2] = {src[0], src[1]};
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t w = (&h[e >> 3].x)[(e & 7) >> 1];
+            const uint16_t bits = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffff);
+            float v;
+            if constexpr (P == P_SPLIT16) v = (float)__builtin_bit_cast(_Float16, bits);
+            else v = __uint_as_float((uint32_t)bits << 16);
+            v *= inv;
+            sq[t][(((e >> 3) ^ swz) << 3) + (e & 7)] = v * v;   // row k = 16 kb + that
+        }
+        __syncthreads();
+        {
+            const int k = t & 15, q = t >> 4;
+            float a = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a += sq[q * 16 + c][k];
+            part[q][k] = a;
+        }
+        __syncthreads();
+        if (t < 16) {
+            float a = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a += part[q][t];
+            J.part[o][(int64_t)b * J.kp + kb * 16 + t] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup: sums the panels' energies per row (FP64), scores the row
+// pairs, ranks them, and writes the split count and the K-block order.  All
+// pairs or none selected keep the natural order (then the contraction is
+// the full split, or the high plane alone, bit for bit).
+__global__ __launch_bounds__(256) void row_select_kernel(SelJob J) {
+    __shared__ double E[3][kMaxSelBlocks * 16];
+    __shared__ double score[kMaxSelBlocks / 2];
+    __shared__ int sorted[kMaxSelBlocks / 2];
+    const int t = threadIdx.x;
+    const int kp = J.kp, np = kp / 32;
+    for (int o = 0; o < 3; ++o)
+        for (int k = t; k < kp; k += 256) {
+            double a = 0.0;
+            for (int b = 0; b < J.panels[o]; ++b) a += (double)J.part[o][(int64_t)b * kp + k];
+            E[o][k] = a;
+        }
+    __syncthreads();
+    // a homocorrelation passes its A plane once (no panels for operand 1)
+    const int o1 = J.panels[1] ? 1 : 0;
+    if (t < np) {
+        double a = 0.0;
+        for (int k = 32 * t; k < 32 * t + 32; ++k) a += E[0][k] * (E[o1][k] + E[2][k]);
+        score[t] = a;
+    }
+    __syncthreads();
+    if (t < np) {
+        int r = 0;
+        for (int q = 0; q < np; ++q)
+            r += (score[q] > score[t] || (score[q] == score[t] && q < t)) ? 1 : 0;
+        sorted[r] = t;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double total = 0.0;
+        for (int r = 0; r < np; ++r) total += score[sorted[r]];
+        // fewest leading pairs whose complement holds at most fmax of the total
+        int c = 0;
+        double tail = total;
+        while (c < np && tail > J.fmax * total) tail -= score[sorted[c++]];
+        J.sel[0] = 2 * c;
+        const bool natural = c == 0 || c == np;
+        for (int r = 0; r < np; ++r) {
+            const int q = natural ? r : sorted[r];
+            J.sel[1 + 2 * r] = 2 * q;
+            J.sel[2 + 2 * r] = 2 * q + 1;
+        }
+    }
+}
+
+hipError_t launch_row_select(const SelJob& J, hipStream_t s) {
+    const int blocks = J.panels[0] + J.panels[1] + J.panels[2];
+    if (J.prec == P_SPLIT16) hipLaunchKernelGGL(row_energy_kernel<P_SPLIT16>, dim3(blocks), dim3(128), 0, s, J);
+    else hipLaunchKernelGGL(row_energy_kernel<P_SPLIT>, dim3(blocks), dim3(128), 0, s, J);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(row_select_kernel, dim3(1), dim3(256), 0, s, J);
+    return hipGetLastError();
 }
 
 // =========================================================================

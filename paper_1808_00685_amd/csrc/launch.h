@@ -110,6 +110,7 @@ hipError_t launch_corr_persistent(int prec, int fm, int fn, bool out_f64, const 
 int corr_variant_supported(int prec, int fm, int fn);
 int persistent_blocks_per_cu(int prec, int fm, int fn, bool out_f64);
 hipError_t launch_interp(const InterpJob& J, hipStream_t s);
+hipError_t launch_row_select(const SelJob& J, hipStream_t s);
 hipError_t launch_tables_qn(const TableSrcInline& src, int blocks, int64_t max_m, hipStream_t s);
 hipError_t launch_tables_qn(const TableSrcArray& src, int blocks, int64_t max_m, hipStream_t s);
 // Workgroups of the Q N kernel for one table: one per frequency 0..floor(m/2).

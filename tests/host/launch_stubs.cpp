@@ -36,6 +36,7 @@ hipError_t launch_corr_persistent(int, int, int, bool, const CorrJob*, const int
     reached("corr_persistent");
 }
 hipError_t launch_interp(const InterpJob&, hipStream_t) { reached("interp"); }
+hipError_t launch_row_select(const SelJob&, hipStream_t) { reached("row_select"); }
 // Every tile and precision pair that passes plan validation is built.
 int corr_variant_supported(int, int, int) { return 1; }
 int persistent_blocks_per_cu(int, int, int, bool) { reached("persistent_blocks_per_cu"); }

@@ -49,9 +49,9 @@ int main() {
     const int64_t ms[] = {2, 3, 11, 64, 127, 128, 256, 300, 1024, 4096};
     const int64_t ns[] = {1, 7, 129, 4096, 16384};
     int ok = 0;
-    for (int prec = 0; prec <= 5; ++prec)
+    for (int prec = 0; prec <= 6; ++prec)
         for (int layout = 0; layout <= 2; ++layout)
-            for (int basis = 0; basis <= 1; ++basis)
+            for (int basis = 0; basis <= 2; ++basis)
                 for (int hil = 0; hil <= 2; ++hil)
                     for (int64_t m : ms)
                         for (int64_t n : ns) {
@@ -73,10 +73,32 @@ int main() {
                             ++ok;
                             EXPECT(info.n_pad >= n && info.k_pad >= m && info.tiles > 0);
                             const bool pow2 = (m & (m - 1)) == 0 && m >= 128 && m <= 1024;
-                            const bool fft = pow2 && (basis == CORR2D_BASIS_FOURIER || hil == CORR2D_HILBERT_NODA);
+                            EXPECT(basis == CORR2D_BASIS_AUTO ? info.basis <= 1 : info.basis == basis);
+                            const bool fft = pow2 && (info.basis == CORR2D_BASIS_FOURIER || hil == CORR2D_HILBERT_NODA);
                             EXPECT(info.transform == (fft ? 1 : 0));
                         }
     EXPECT(ok > 1000);
+
+    // row-selective split: split formats, Fourier basis, m <= 1024
+    for (int prec : {CORR2D_PREC_SPLIT_BF16, CORR2D_PREC_SPLIT_F16, CORR2D_PREC_F32})
+        for (int64_t m : ms)
+            for (int64_t n2 : {(int64_t)0, (int64_t)300}) {
+                corr2d_desc_init(&d);
+                d.m = m;
+                d.n1 = 4096;
+                d.n2 = n2;
+                d.prec = prec;
+                d.flags = CORR2D_FLAG_SPLIT_ROWS;
+                d.split_tol = 1e-4;
+                corr2d_plan_info info;
+                const corr2d_status s = try_plan(d, &info);
+                if (prec == CORR2D_PREC_F32 || m > 1024) {
+                    EXPECT(s == CORR2D_EUNSUPPORTED);
+                    continue;
+                }
+                EXPECT(s == CORR2D_OK);
+                EXPECT(info.sel_offset > 0 && info.sel_offset + 65 * 4 <= info.workspace_bytes);
+            }
 
     // heterocorrelation, strides, result scaling, flags
     corr2d_desc_init(&d);

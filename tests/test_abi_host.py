@@ -110,6 +110,23 @@ def test_auto_basis_resolution(prec, hilbert, expect):
     assert q.info.basis == B.BASIS["fourier"]
 
 
+def test_row_select_plan_workspace_and_info():
+    """A row-selective plan reserves the energy partials and the selection
+    record (reported by plan info); other plans report no record."""
+    p = B.Plan(m=256, n1=16384, n2=0, prec="split_bf16", flags=B.FLAG_SPLIT_ROWS,
+               out_layout="upper_aligned")
+    q = B.Plan(m=256, n1=16384, n2=0, prec="split_bf16", out_layout="upper_aligned")
+    assert q.info.sel_offset == 0
+    assert p.info.sel_offset > 0 and p.info.sel_offset % 256 == 0
+    assert p.info.sel_offset + 4 * 65 <= p.ws_bytes
+    # energies: (n_pad/128) panels x k_pad floats for operands 0 and 2
+    assert p.ws_bytes - q.ws_bytes >= 2 * 128 * 256 * 4
+    h = B.Plan(m=128, n1=8192, n2=2048, prec="split_f16", flags=B.FLAG_SPLIT_ROWS)
+    assert h.info.sel_offset > 0
+    with pytest.raises(B.Corr2dError):
+        B.Plan(B.corr2d_desc_init(prec="split_bf16", flags=B.FLAG_SPLIT_ROWS), items=[(16, 100, 0, 0, 0)])
+
+
 def test_split_f16_plan_scales_per_band():
     p = B.Plan(m=256, n1=4096, n2=0, prec="split_f16")
     assert p.info.per_band_scale == 1 and p.info.k_pad == 256 and p.info.transform == 1
@@ -148,7 +165,15 @@ def _plan_status(**kw):
     (dict(out_layout=2), B.OK),
     (dict(prec=5, flags=B.FLAG_NO_PER_BAND_SCALE), B.EUNSUPPORTED),
     (dict(flags=0x100), B.EINVAL),
-    (dict(flags=0x20), B.EINVAL),
+    (dict(flags=0x40), B.EINVAL),
+    (dict(flags=B.FLAG_SPLIT_ROWS), B.OK),
+    (dict(flags=B.FLAG_SPLIT_ROWS, prec="split_f16"), B.OK),
+    (dict(flags=B.FLAG_SPLIT_ROWS, prec="f32"), B.EUNSUPPORTED),
+    (dict(flags=B.FLAG_SPLIT_ROWS, basis="time"), B.EUNSUPPORTED),
+    (dict(flags=B.FLAG_SPLIT_ROWS, m=1100), B.EUNSUPPORTED),
+    (dict(flags=B.FLAG_SPLIT_ROWS, m=1024), B.OK),
+    (dict(split_tol=-1.0), B.EINVAL),
+    (dict(split_tol=float("nan")), B.EINVAL),
     (dict(flags=B.FLAG_TRANSFORM_MATMUL), B.OK),
     (dict(tile=7), B.EINVAL),
     (dict(prec=0, tile=2), B.OK),

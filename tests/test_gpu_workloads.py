@@ -49,6 +49,8 @@ def large():
     ("split_bf16", "fourier", TOL["split_bf16"], B.FLAG_TRANSFORM_MATMUL, "upper_packed"),
     ("f32", "fourier", TOL["f32"], 0, "upper_aligned"),
     ("split_f16", "fourier", TOL["split_f16"], 0, "upper_aligned"),
+    ("split_f16", "fourier", TOL["split_f16"], B.FLAG_SPLIT_ROWS, "upper_aligned"),
+    ("split_bf16", "fourier", TOL["split_bf16"], B.FLAG_SPLIT_ROWS, "upper_aligned"),
     ("bf16", "auto", BF16_BAND_TOL, 0, "upper_aligned"),
     ("bf16", "fourier", TOL["bf16"], 0, "upper_aligned"),
 ])
@@ -66,11 +68,16 @@ def test_large_homo_full(gpu, large, prec, basis, tol, flags, layout):
     phi, psi, plan, ws = B.homo(torch.as_tensor(S, device=gpu), prec=prec, basis=basis,
                                 layout=layout, flags=flags)
     torch.cuda.synchronize()
-    assert B.corr2d_plan_get_info(plan.handle).transform == (0 if flags else 1)
+    rowsel = bool(flags & B.FLAG_SPLIT_ROWS)
+    assert B.corr2d_plan_get_info(plan.handle).transform == (0 if flags & B.FLAG_TRANSFORM_MATMUL else 1)
     rows = aligned_rows if layout == "upper_aligned" else packed_rows
     planes = (phi, psi)
+    # the row-selective split leaves chosen rows to hi*hi: no per-element bound
     fe = homo_full_error(blocks, lambda k, r0, r1: rows(planes[k], n, r0, r1),
-                         tau=ELEMENT_TAU[prec])
+                         tau=None if rowsel else ELEMENT_TAU[prec])
+    if rowsel:
+        nsel, order = B.selection(ws, plan)
+        print(f"large {prec} row-selective: {nsel} of {len(order)} K blocks carry the low plane")
     e_phi, e_psi = fe.rel(0), fe.rel(1)
     print(f"large {prec}/{basis}/flags={flags}/{layout}: full-matrix rel.err phi={e_phi:.3e} "
           f"psi={e_psi:.3e} (largest error/bound {fe.bound_ratio:.3f})")
