@@ -306,6 +306,24 @@ corr2d_status corr2d_plan_get_info(corr2d_plan_t plan, corr2d_plan_info* info);
 corr2d_status corr2d_homo(corr2d_plan_t plan, const void* y, const double* ref,
                           void* phi, void* psi, void* ws, size_t ws_bytes, void* stream);
 
+/* corr2d_homo for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation with no workspace argument.  The library's fixed device
+ * scratch of CORR2D_NOALLOC_SCRATCH_BYTES (one copy per GPU, held until the
+ * process ends) serves as the workspace; the call makes no hipMalloc,
+ * hipFree, hipHostMalloc or other allocating call.
+ *   EWORKSPACE   the plan's workspace (corr2d_workspace_bytes) exceeds the
+ *                scratch (m = 256, n = 16384 fits in split-BF16, FP32, BF16)
+ *   EUNSUPPORTED an interpolation plan (its weights go through pinned memory)
+ *   EINVAL       as corr2d_homo
+ * Every call on one GPU uses that GPU's scratch: calls that overlap on one
+ * GPU (other streams, other threads) race and must be serialized by the
+ * caller.  Nothing in the scratch needs clearing between calls: each call
+ * writes every scratch byte it reads.                                        */
+#define CORR2D_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+corr2d_status corr2d_homo_noalloc(corr2d_plan_t plan, const void* y, const double* ref,
+                                  void* phi, void* psi, void* stream);
+
 /* Heterocorrelation, corr2d(Mat1, Mat2) (Sec. 3): two data sets sharing the
  * m perturbation steps.  Psi(nu1, nu2) = Y1^T H Y2 -- the Hilbert transform
  * acts on the second set (Eq. (disHTasyn)).  ref1/ref2 independently NULL for

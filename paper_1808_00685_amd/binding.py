@@ -35,8 +35,9 @@ EXPORTED = [
     "corr2d_desc_init", "corr2d_plan", "corr2d_batched_plan", "corr2d_plan_destroy",
     "corr2d_workspace_bytes", "corr2d_plan_get_info", "corr2d_homo", "corr2d_hetero",
     "corr2d_batched", "corr2d_status_str", "corr2d_last_error", "corr2d_version",
-    "corr2d_set_timing_events",
+    "corr2d_set_timing_events", "corr2d_homo_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 64 << 20   # CORR2D_NOALLOC_SCRATCH_BYTES
 
 
 class corr2d_desc(ctypes.Structure):
@@ -99,6 +100,8 @@ def lib():
         L.corr2d_plan_get_info.restype = st
         L.corr2d_homo.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
         L.corr2d_homo.restype = st
+        L.corr2d_homo_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.corr2d_homo_noalloc.restype = st
         L.corr2d_hetero.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.corr2d_hetero.restype = st
         L.corr2d_batched.argtypes = [vp, vp, vp, vp, vp, sz, vp]
@@ -234,6 +237,11 @@ def corr2d_homo(plan, y, ref, phi, psi, ws, ws_bytes=None, stream=None, check=Tr
         ws_bytes = ws.numel() * ws.element_size()
     s = lib().corr2d_homo(plan, _ptr(y), _ptr(ref), _ptr(phi), _ptr(psi), _ptr(ws), ws_bytes,
                           _stream(stream))
+    return _check(s) if check else s
+
+
+def corr2d_homo_noalloc(plan, y, ref, phi, psi, stream=None, check=True):
+    s = lib().corr2d_homo_noalloc(plan, _ptr(y), _ptr(ref), _ptr(phi), _ptr(psi), _stream(stream))
     return _check(s) if check else s
 
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorr2d.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels.hip", "api.cpp", "tune.cpp", "interp.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "tune.cpp", "interp.cpp", "noalloc.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = [

@@ -1002,6 +1002,31 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Checks of the allocation-free entry point (noalloc.hip)
+// ---------------------------------------------------------------------------
+namespace corr2d {
+
+corr2d_status noalloc_fail(corr2d_status s, const char* what) { return fail(s, "%s", what); }
+
+corr2d_status noalloc_check(corr2d_plan_t p, size_t max_bytes) {
+    if (!p) return fail(CORR2D_EINVAL, "NULL plan");
+    if (p->batched || p->hetero)
+        return fail(CORR2D_EINVAL, "corr2d_homo_noalloc takes a homocorrelation plan");
+    if (p->interp)
+        return fail(CORR2D_EUNSUPPORTED,
+                    "corr2d_homo_noalloc: interpolation plans stage their weights in pinned memory; "
+                    "use corr2d_homo");
+    if (p->ws_bytes > max_bytes)
+        return fail(CORR2D_EWORKSPACE,
+                    "corr2d_homo_noalloc: the plan needs a workspace of %zu bytes, more than the %zu "
+                    "bytes of the fixed scratch; use corr2d_homo with a workspace",
+                    p->ws_bytes, max_bytes);
+    return CORR2D_OK;
+}
+
+}  // namespace corr2d
+
+// ---------------------------------------------------------------------------
 // Batched path
 // ---------------------------------------------------------------------------
 namespace {

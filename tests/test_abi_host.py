@@ -435,3 +435,33 @@ def test_result_object_argument_errors_before_any_call():
     with pytest.raises(ValueError):
         B.hetero(y, torch.zeros(9, 10, dtype=torch.float64))
 
+
+def test_noalloc_scratch_size_matches_header(tmp_path):
+    src = tmp_path / "s.c"
+    src.write_text('#include <stdio.h>\n#include "corr2d.h"\n'
+                   'int main(void){printf("%zu\\n", CORR2D_NOALLOC_SCRATCH_BYTES); return 0;}\n')
+    exe = tmp_path / "s"
+    r = subprocess.run(["gcc", "-I" + os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert int(subprocess.run([str(exe)], capture_output=True, text=True).stdout) == \
+        B.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_before_device_work():
+    """The allocation-free entry point checks the plan before any HIP call:
+    a NULL plan, a heterocorrelation or batched plan, an interpolation plan,
+    and a plan whose workspace exceeds the fixed scratch."""
+    L = B.lib()
+    st = L.corr2d_homo_noalloc(None, None, None, None, None, None)
+    assert st == B.EINVAL
+    het = B.Plan(m=16, n1=64, n2=32, prec="f32")
+    assert B.corr2d_homo_noalloc(het.handle, 1, None, 1, 1, check=False) == B.EINVAL
+    it = B.Plan(m=8, n1=64, n2=0, prec="f32", t_in=np.linspace(0.0, 1.0, 9) ** 2, interp="linear")
+    assert B.corr2d_homo_noalloc(it.handle, 1, None, 1, 1, check=False) == B.EUNSUPPORTED
+    big = B.Plan(m=256, n1=16384, n2=0, prec="f64", out_layout="upper_aligned", out_dtype="f64")
+    assert big.ws_bytes > B.NOALLOC_SCRATCH_BYTES
+    assert B.corr2d_homo_noalloc(big.handle, 1, None, 1, 1, check=False) == B.EWORKSPACE
+    assert b"fixed scratch" in L.corr2d_last_error()
+    fits = B.Plan(m=256, n1=16384, n2=0, prec="split_bf16", out_layout="upper_aligned")
+    assert fits.ws_bytes <= B.NOALLOC_SCRATCH_BYTES
