@@ -554,6 +554,67 @@ def batch_workload(B, torch, oracle, synth, dev, otimes):
     return rows
 
 
+def profile_run(B, torch, synth, dev, spec, reps):
+    """Only the calls of one workload, for profiler runs (--profile
+    WORKLOAD:PREC[:rowsel]); prints one JSON line with the mean wall time."""
+    parts = spec.split(":")
+    work, prec = parts[0], parts[1]
+    flags = B.FLAG_SPLIT_ROWS if "rowsel" in parts[2:] else 0
+    out_dtype = "f64" if prec == "f64" else "f32"
+    tdt = torch.float64 if out_dtype == "f64" else torch.float32
+    if work == "large":
+        S, _ = synth.workload_large()
+        m, n = S.shape
+        y = torch.as_tensor(S, device=dev)
+        plan = B.Plan(m=m, n1=n, n2=0, prec=prec, out_layout="upper_aligned", in_dtype="f64",
+                      out_dtype=out_dtype, flags=flags)
+        numel = B.out_elements("upper_aligned", n)
+        phi = torch.empty(numel, dtype=tdt, device=dev)
+        psi = torch.empty(numel, dtype=tdt, device=dev)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
+    elif work == "medium":
+        S, _ = synth.workload_medium()
+        m, n = S.shape
+        y = torch.as_tensor(S, device=dev)
+        plan = B.Plan(m=m, n1=n, n2=0, prec=prec, in_dtype="f64", out_dtype=out_dtype, flags=flags)
+        phi = torch.empty(n * n, dtype=tdt, device=dev)
+        psi = torch.empty(n * n, dtype=tdt, device=dev)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_homo(plan.handle, y, None, phi, psi, ws)
+    elif work == "hetero":
+        S1, S2, _ = synth.workload_hetero()
+        y1, y2 = torch.as_tensor(S1, device=dev), torch.as_tensor(S2, device=dev)
+        n1, n2 = S1.shape[1], S2.shape[1]
+        plan = B.Plan(m=S1.shape[0], n1=n1, n2=n2, prec=prec, in_dtype="f64", out_dtype=out_dtype,
+                      flags=flags)
+        phi = torch.empty(n1 * n2, dtype=tdt, device=dev)
+        psi = torch.empty(n1 * n2, dtype=tdt, device=dev)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_hetero(plan.handle, y1, None, y2, None, phi, psi, ws)
+    elif work == "batch":
+        items = synth.batch_spec()
+        offs, ooffs, cur, ocur = [], [], 0, 0
+        for it in items:
+            offs.append(cur)
+            ooffs.append(ocur)
+            cur += it.m * it.n
+            ocur += it.n * (it.n + 1) // 2
+        y = torch.empty(cur, dtype=torch.float64, device=dev)
+        for it, o in zip(items, offs):
+            y[o:o + it.m * it.n] = torch.as_tensor(synth.batch_item_data(it).ravel(), device=dev)
+        plan = B.Plan(B.corr2d_desc_init(prec=prec, out_layout="upper_packed", flags=flags),
+                      items=[(it.m, it.n, o, 0, oo) for it, o, oo in zip(items, offs, ooffs)])
+        phi = torch.empty(ocur, dtype=torch.float32, device=dev)
+        psi = torch.empty(ocur, dtype=torch.float32, device=dev)
+        ws = plan.workspace(dev)
+        call = lambda: B.corr2d_batched(plan.handle, y, phi, psi, ws)
+    else:
+        raise SystemExit(f"unknown workload {work}")
+    ms = time_calls(torch, call, reps, batches=1)
+    print(json.dumps({"profile": spec, "ms_per_call": ms, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,6 +631,9 @@ def main():
                     help="storage of the upper triangle in the headline line")
     ap.add_argument("--table1", action="store_true",
                     help="instead of the benchmark line, time the paper's Table 1 grid (FP64, FP32)")
+    ap.add_argument("--profile", metavar="WORKLOAD:PREC[:rowsel]",
+                    help="instead of the benchmark line, only call one workload (large, medium, "
+                         "hetero, batch) --steps times, for profiler runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -588,6 +652,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
+    if args.profile:
+        profile_run(B, torch, synth, dev, args.profile, args.steps)
+        return
     if args.table1:
         print(json.dumps({"table1": table1_sweep(B, torch, synth, dev), "paper": paper_context()}),
               flush=True)

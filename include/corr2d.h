@@ -147,7 +147,7 @@ typedef enum corr2d_dtype { CORR2D_DTYPE_F64 = 0, CORR2D_DTYPE_F32 = 1 } corr2d_
  * keeps the low plane for the fewest leading pairs whose complement holds
  * at most the fraction of that energy which the target desc.split_tol
  * allows (the modelled relative error of Phi from the rows left to hi*hi
- * is a quarter of the target).  The target bounds Phi's modelled error; Psi
+ * is an eighth of the target).  The target bounds Phi's modelled error; Psi
  * follows it unless Psi itself cancels strongly.  The selection is written
  * to the workspace (plan info sel_offset).                                 */
 #define CORR2D_FLAG_SPLIT_ROWS 0x20u

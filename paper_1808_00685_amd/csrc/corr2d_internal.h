@@ -118,10 +118,13 @@ constexpr int64_t kNearStoreBytes = int64_t(192) << 20;
 // their products, and the fewest leading pairs whose complement holds at
 // most fmax of that energy keep the low plane.
 constexpr int kMaxSelBlocks = 64;   // K blocks a selection orders (kp <= 1024)
+constexpr int kSelGroup = 8;        // panels of 128 points per energy workgroup
+__host__ __device__ constexpr int sel_groups(int panels) { return (panels + kSelGroup - 1) / kSelGroup; }
 struct SelJob {
     const void* X[3];      // high planes (panel-blocked)
     const float* s[3];     // per-band scales (nullptr: unscaled)
-    float* part[3];        // per-panel row energies: panels_o x kp floats each
+    float* part[3];        // row energies per group of kSelGroup panels:
+                           // sel_groups(panels_o) x kp floats each
     int32_t panels[3];     // column panels of 128 per operand
     int32_t kp;
     int32_t prec;

@@ -2145,37 +2145,49 @@ __global__ __launch_bounds__(256, FM * FN < 16 ? 2 : 1) void corr_persistent_ker
 // =========================================================================
 // Row selection of the split formats
 // =========================================================================
-// Energy of every packed Fourier row of one operand over one panel of 128
-// spectral points (workgroups in turn over the panels of operands 0, 1, 2;
-// operand 1 has none for a homocorrelation, whose right A is its left A):
-// thread t reads its point's 16 values of each K block
-// (32 bytes, the halves swapped as the panel-blocked layout stores them),
-// unscaled, and the workgroup sums their squares per row through LDS.
+// Energy of every packed Fourier row of one operand over a group of up to
+// kSelGroup panels of 128 spectral points (workgroups in turn over the
+// groups of operands 0, 1, 2; operand 1 has none for a homocorrelation,
+// whose right A is its left A): thread t reads its point's 16 values of each
+// K block in each panel of the group (32 bytes, the halves swapped as the
+// panel-blocked layout stores them), unscaled, sums their squares per row,
+// and the workgroup adds its threads' sums through LDS.
 template <int P>
 __global__ __launch_bounds__(128) void row_energy_kernel(SelJob J) {
     __shared__ float sq[128][17];
     __shared__ float part[8][16];
     int b = blockIdx.x, o = 0;
-    while (o < 2 && b >= J.panels[o]) b -= J.panels[o++];
+    while (o < 2 && b >= sel_groups(J.panels[o])) b -= sel_groups(J.panels[o++]);
     const int t = threadIdx.x;
     const int nkb = J.kp >> 4;
-    const int64_t i = (int64_t)b * 128 + t;   // spectral point
-    const float inv = J.s[o] ? 1.0f / J.s[o][i] : 1.0f;   // power of two: exact
+    const int p0 = b * kSelGroup, p1 = min(p0 + kSelGroup, J.panels[o]);
     const uint16_t* X = (const uint16_t*)J.X[o];
-    const int swz = row_swizzle(i);
+    // the halves' swap depends on bits 2 and 3 of the point index only: the
+    // same for this thread's point in every panel
+    const int swz = row_swizzle(t);
     for (int kb = 0; kb < nkb; ++kb) {
-        const uint4* src = (const uint4*)(X + (((int64_t)b * nkb + kb) * 128 + t) * 16);
-        const uint4 h[2] = {src[0], src[1]};
+        float acc[16];   // in stored order
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint32_t w = (&h[e >> 3].x)[(e & 7) >> 1];
-            const uint16_t bits = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffff);
-            float v;
-            if constexpr (P == P_SPLIT16) v = (float)__builtin_bit_cast(_Float16, bits);
-            else v = __uint_as_float((uint32_t)bits << 16);
-            v *= inv;
-            sq[t][(((e >> 3) ^ swz) << 3) + (e & 7)] = v * v;   // row k = 16 kb + that
+        for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+        for (int pn = p0; pn < p1; ++pn) {
+            const int64_t i = (int64_t)pn * 128 + t;   // spectral point
+            const float inv = J.s[o] ? 1.0f / J.s[o][i] : 1.0f;   // power of two: exact
+            const uint4* src = (const uint4*)(X + (((int64_t)pn * nkb + kb) * 128 + t) * 16);
+            const uint4 h[2] = {src[0], src[1]};
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t w = (&h[e >> 3].x)[(e & 7) >> 1];
+                const uint16_t bits = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffff);
+                float v;
+                if constexpr (P == P_SPLIT16) v = (float)__builtin_bit_cast(_Float16, bits);
+                else v = __uint_as_float((uint32_t)bits << 16);
+                v *= inv;
+                acc[e] += v * v;
+            }
         }
+        // stored position e holds row 16 kb + (e ^ 8 swz)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sq[t][e ^ (swz << 3)] = acc[e];
         __syncthreads();
         {
             const int k = t & 15, q = t >> 4;
@@ -2195,22 +2207,29 @@ __global__ __launch_bounds__(128) void row_energy_kernel(SelJob J) {
     }
 }
 
-// One workgroup: sums the panels' energies per row (FP64), scores the row
+// One workgroup: sums the groups' energies per row (FP64), scores the row
 // pairs, ranks them, and writes the split count and the K-block order.  All
 // pairs or none selected keep the natural order (then the contraction is
 // the full split, or the high plane alone, bit for bit).
-__global__ __launch_bounds__(256) void row_select_kernel(SelJob J) {
+__global__ __launch_bounds__(1024) void row_select_kernel(SelJob J) {
     __shared__ double E[3][kMaxSelBlocks * 16];
     __shared__ double score[kMaxSelBlocks / 2];
     __shared__ int sorted[kMaxSelBlocks / 2];
     const int t = threadIdx.x;
     const int kp = J.kp, np = kp / 32;
-    for (int o = 0; o < 3; ++o)
-        for (int k = t; k < kp; k += 256) {
-            double a = 0.0;
-            for (int b = 0; b < J.panels[o]; ++b) a += (double)J.part[o][(int64_t)b * kp + k];
-            E[o][k] = a;
+    for (int o = 0; o < 3; ++o) {
+        const int ng = sel_groups(J.panels[o]);
+        for (int k = t; k < kp; k += 1024) {
+            // independent partial sums, so that the loads overlap
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
+            int g = 0;
+            for (; g + 4 <= ng; g += 4)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] += (double)J.part[o][(int64_t)(g + q) * kp + k];
+            for (; g < ng; ++g) a[0] += (double)J.part[o][(int64_t)g * kp + k];
+            E[o][k] = (a[0] + a[1]) + (a[2] + a[3]);
         }
+    }
     __syncthreads();
     // a homocorrelation passes its A plane once (no panels for operand 1)
     const int o1 = J.panels[1] ? 1 : 0;
@@ -2245,12 +2264,12 @@ __global__ __launch_bounds__(256) void row_select_kernel(SelJob J) {
 }
 
 hipError_t launch_row_select(const SelJob& J, hipStream_t s) {
-    const int blocks = J.panels[0] + J.panels[1] + J.panels[2];
+    const int blocks = sel_groups(J.panels[0]) + sel_groups(J.panels[1]) + sel_groups(J.panels[2]);
     if (J.prec == P_SPLIT16) hipLaunchKernelGGL(row_energy_kernel<P_SPLIT16>, dim3(blocks), dim3(128), 0, s, J);
     else hipLaunchKernelGGL(row_energy_kernel<P_SPLIT>, dim3(blocks), dim3(128), 0, s, J);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(row_select_kernel, dim3(1), dim3(256), 0, s, J);
+    hipLaunchKernelGGL(row_select_kernel, dim3(1), dim3(1024), 0, s, J);
     return hipGetLastError();
 }
 

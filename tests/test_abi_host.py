@@ -119,8 +119,8 @@ def test_row_select_plan_workspace_and_info():
     assert q.info.sel_offset == 0
     assert p.info.sel_offset > 0 and p.info.sel_offset % 256 == 0
     assert p.info.sel_offset + 4 * 65 <= p.ws_bytes
-    # energies: (n_pad/128) panels x k_pad floats for operands 0 and 2
-    assert p.ws_bytes - q.ws_bytes >= 2 * 128 * 256 * 4
+    # energies: (n_pad/128/8) panel groups x k_pad floats for operands 0 and 2
+    assert p.ws_bytes - q.ws_bytes >= 2 * 16 * 256 * 4
     h = B.Plan(m=128, n1=8192, n2=2048, prec="split_f16", flags=B.FLAG_SPLIT_ROWS)
     assert h.info.sel_offset > 0
     with pytest.raises(B.Corr2dError):
