@@ -2145,65 +2145,71 @@ __global__ __launch_bounds__(256, FM * FN < 16 ? 2 : 1) void corr_persistent_ker
 // =========================================================================
 // Row selection of the split formats
 // =========================================================================
-// Energy of every packed Fourier row of one operand over a group of up to
-// kSelGroup panels of 128 spectral points (workgroups in turn over the
-// groups of operands 0, 1, 2; operand 1 has none for a homocorrelation,
-// whose right A is its left A): thread t reads its point's 16 values of each
-// K block in each panel of the group (32 bytes, the halves swapped as the
+// Energy of the 16 packed Fourier rows of one K block of one operand over a
+// group of up to kSelGroup panels of 128 spectral points (workgroups in turn
+// over the groups and K blocks of operands 0, 1, 2; operand 1 has none for a
+// homocorrelation, whose right A is its left A): thread t reads its point's
+// 16 values in each panel of the group (32 bytes, the halves swapped as the
 // panel-blocked layout stores them), unscaled, sums their squares per row,
 // and the workgroup adds its threads' sums through LDS.
 template <int P>
 __global__ __launch_bounds__(128) void row_energy_kernel(SelJob J) {
     __shared__ float sq[128][17];
     __shared__ float part[8][16];
-    int b = blockIdx.x, o = 0;
-    while (o < 2 && b >= sel_groups(J.panels[o])) b -= sel_groups(J.panels[o++]);
-    const int t = threadIdx.x;
     const int nkb = J.kp >> 4;
-    const int p0 = b * kSelGroup, p1 = min(p0 + kSelGroup, J.panels[o]);
+    int b = blockIdx.x, o = 0;
+    while (o < 2 && b >= sel_groups(J.panels[o]) * nkb) b -= sel_groups(J.panels[o++]) * nkb;
+    const int grp = b / nkb, kb = b % nkb;
+    const int t = threadIdx.x;
+    const int p0 = grp * kSelGroup, np = min(kSelGroup, J.panels[o] - p0);
     const uint16_t* X = (const uint16_t*)J.X[o];
     // the halves' swap depends on bits 2 and 3 of the point index only: the
     // same for this thread's point in every panel
     const int swz = row_swizzle(t);
-    for (int kb = 0; kb < nkb; ++kb) {
-        float acc[16];   // in stored order
+    uint4 h[kSelGroup][2];
+    float inv[kSelGroup];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
-        for (int pn = p0; pn < p1; ++pn) {
-            const int64_t i = (int64_t)pn * 128 + t;   // spectral point
-            const float inv = J.s[o] ? 1.0f / J.s[o][i] : 1.0f;   // power of two: exact
-            const uint4* src = (const uint4*)(X + (((int64_t)pn * nkb + kb) * 128 + t) * 16);
-            const uint4 h[2] = {src[0], src[1]};
+    for (int q = 0; q < kSelGroup; ++q) {
+        const int pn = p0 + min(q, np - 1);   // past the group's end: reread its last panel, dropped below
+        const uint4* src = (const uint4*)(X + (((int64_t)pn * nkb + kb) * 128 + t) * 16);
+        h[q][0] = src[0];
+        h[q][1] = src[1];
+        inv[q] = J.s[o] ? 1.0f / J.s[o][(int64_t)pn * 128 + t] : 1.0f;   // power of two: exact
+    }
+    float acc[16];   // in stored order
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t w = (&h[e >> 3].x)[(e & 7) >> 1];
-                const uint16_t bits = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffff);
-                float v;
-                if constexpr (P == P_SPLIT16) v = (float)__builtin_bit_cast(_Float16, bits);
-                else v = __uint_as_float((uint32_t)bits << 16);
-                v *= inv;
-                acc[e] += v * v;
-            }
+    for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kSelGroup; ++q) {
+        if (q >= np) break;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t w = (&h[q][e >> 3].x)[(e & 7) >> 1];
+            const uint16_t bits = (e & 1) ? (uint16_t)(w >> 16) : (uint16_t)(w & 0xffff);
+            float v;
+            if constexpr (P == P_SPLIT16) v = (float)__builtin_bit_cast(_Float16, bits);
+            else v = __uint_as_float((uint32_t)bits << 16);
+            v *= inv[q];
+            acc[e] += v * v;
         }
-        // stored position e holds row 16 kb + (e ^ 8 swz)
+    }
+    // stored position e holds row 16 kb + (e ^ 8 swz)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) sq[t][e ^ (swz << 3)] = acc[e];
-        __syncthreads();
-        {
-            const int k = t & 15, q = t >> 4;
-            float a = 0.0f;
+    for (int e = 0; e < 16; ++e) sq[t][e ^ (swz << 3)] = acc[e];
+    __syncthreads();
+    {
+        const int k = t & 15, q = t >> 4;
+        float a = 0.0f;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) a += sq[q * 16 + c][k];
-            part[q][k] = a;
-        }
-        __syncthreads();
-        if (t < 16) {
-            float a = 0.0f;
+        for (int c = 0; c < 16; ++c) a += sq[q * 16 + c][k];
+        part[q][k] = a;
+    }
+    __syncthreads();
+    if (t < 16) {
+        float a = 0.0f;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a += part[q][t];
-            J.part[o][(int64_t)b * J.kp + kb * 16 + t] = a;
-        }
-        __syncthreads();
+        for (int q = 0; q < 8; ++q) a += part[q][t];
+        J.part[o][(int64_t)grp * J.kp + kb * 16 + t] = a;
     }
 }
 
@@ -2264,7 +2270,7 @@ __global__ __launch_bounds__(1024) void row_select_kernel(SelJob J) {
 }
 
 hipError_t launch_row_select(const SelJob& J, hipStream_t s) {
-    const int blocks = sel_groups(J.panels[0]) + sel_groups(J.panels[1]) + sel_groups(J.panels[2]);
+    const int blocks = (sel_groups(J.panels[0]) + sel_groups(J.panels[1]) + sel_groups(J.panels[2])) * (J.kp >> 4);
     if (J.prec == P_SPLIT16) hipLaunchKernelGGL(row_energy_kernel<P_SPLIT16>, dim3(blocks), dim3(128), 0, s, J);
     else hipLaunchKernelGGL(row_energy_kernel<P_SPLIT>, dim3(blocks), dim3(128), 0, s, J);
     hipError_t e = hipGetLastError();
