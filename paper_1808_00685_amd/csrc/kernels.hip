@@ -1852,8 +1852,8 @@ __device__ inline void wait_units(int u) {
 // others are copied and multiplied with the high plane alone (hi*hi).  A
 // stage then holds one or two planes, and the waits count the copies of
 // the stages actually in flight.
-template <int P, int TM>
-__device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int* sexp) {
+template <int P, int TM, bool SEL>
+__device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int* sexp, int* sorder) {
     using FT = typename Wide<P>::T;
     constexpr int PL = planes(P);
     constexpr int S = ring_stages<P, TM>();
@@ -1872,14 +1872,25 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
     const int wi = w >> 1, wj = w & 1;
     const int nkb = C.kp >> 4;
     const int64_t panel_bytes = (int64_t)nkb * 4096;
-    // K-block order and split count: lane l holds the l-th block of the
-    // order (nkb <= 64 where a list is given); nsel blocks carry both planes
-    // (clamped, so that a damaged list cannot send a copy out of range)
-    const bool listed = PL == 2 && C.kb_sel != nullptr;
-    const int nsel = PL == 1 ? 0
-                     : (listed ? min(max(__builtin_amdgcn_readfirstlane(C.kb_sel[0]), 0), nkb) & ~1 : nkb);
-    const int order = listed && lane < nkb ? min(max(C.kb_sel[1 + lane], 0), nkb - 1) : lane;
-    auto block_of = [&](int kb) { return listed ? __builtin_amdgcn_readlane(order, kb) : kb; };
+    // Row-selective split (SEL, split formats): the K-block order goes to
+    // an LDS table (nkb <= 64), read per copy; nsel blocks carry both
+    // planes (clamped, so that a damaged record cannot send a copy out of
+    // range).  Without SEL every stage has the format's planes, in order.
+    // (Kept in LDS rather than in a register: a block index read from a
+    // loaded register made the compiler wait for every copy in flight
+    // before the fragment reads.)
+    static_assert(!SEL || PL == 2, "row selection is for the split formats");
+    int nsel = PL == 1 ? 0 : nkb;
+    if constexpr (SEL) {
+        nsel = min(max(__builtin_amdgcn_readfirstlane(C.kb_sel[0]), 0), nkb) & ~1;
+        if (tid < kMaxSelBlocks) sorder[tid] = tid < nkb ? min(max(C.kb_sel[1 + tid], 0), nkb - 1) : 0;
+        wait_lgkm0();
+        __syncthreads();   // the table is written before the first copy reads it
+    }
+    auto block_of = [&](int kb) {
+        if constexpr (SEL) return __builtin_amdgcn_readfirstlane(sorder[kb]);
+        else return kb;
+    };
     auto planes_of = [&](int kb) { return kb < nsel ? PL : 1; };
 
     const char* src[PL][CPW];
@@ -1901,14 +1912,22 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
     auto issue = [&](int kb) {
         char* dst = lds + (kb % S) * SB;
         const int64_t off = (int64_t)block_of(kb) * 4096;
-        const int np = planes_of(kb);
+        const int np = SEL ? planes_of(kb) : PL;
 #pragma unroll
         for (int p = 0; p < PL; ++p)
             if (p < np)
 #pragma unroll
-                for (int k = 0; k < CPW; ++k)
-                    __builtin_amdgcn_global_load_lds(AS_GLOBAL(src[p][k] + off),
-                                                     AS_LDS(dst + p * PB + (w + k * NW) * 1024), 16, 0, 0);
+                for (int k = 0; k < CPW; ++k) {
+                    // The LDS destination passes through an empty asm, so the
+                    // compiler cannot tell which LDS object the copy writes:
+                    // it then leaves the ordering of copies and fragment reads
+                    // to the explicit waits of the ring (it would otherwise
+                    // wait for every copy in flight, the prefetches included,
+                    // before reading a stage whose copy has landed).
+                    char* d = dst + p * PB + (w + k * NW) * 1024;
+                    asm volatile("" : "+v"(d));
+                    __builtin_amdgcn_global_load_lds(AS_GLOBAL(src[p][k] + off), AS_LDS(d), 16, 0, 0);
+                }
     };
     // plane-stages of stages lo..hi (inclusive, clipped to the K range): a
     // wave issues CPW copies for each
@@ -1984,7 +2003,8 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
     // kb+S-1 may still be in flight (a wave's vector memory operations
     // complete in issue order).
     auto step = [&](const auto& Fc, auto& Fn, int kb) {
-        wait_units<CPW, MAXU>(units(kb + 2, kb + S - 1));
+        if constexpr (SEL) wait_units<CPW, MAXU>(units(kb + 2, kb + S - 1));
+        else wait_units<CPW * PL, S - 2>(min(S - 2, nkb - 2 - kb));
         wait_lgkm0();
         lds_barrier();
         if (kb + S < nkb) issue(kb + S);
@@ -2010,12 +2030,13 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
 #pragma unroll
     for (int st = 0; st < S; ++st)
         if (st < nkb) issue(st);
-    wait_units<CPW, MAXU>(units(1, S - 1));
+    if constexpr (SEL) wait_units<CPW, MAXU>(units(1, S - 1));
+    else wait_units<CPW * PL, S - 1>(min(S - 1, nkb - 1));
     lds_barrier();
     // nkb and nsel are even and nkb is at least 2: pairs of steps, then the
     // last pair, whose second stage needs no further load (every load has
     // landed and is visible after the last step's barrier)
-    if (PL == 1 || nsel == nkb) {
+    if (!SEL || nsel == nkb) {
         // every stage with all the format's planes
         StageFrags<FT, PL> F0, F1;
         load_frags(F0, 0);
@@ -2025,7 +2046,7 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
         }
         step(F0, F1, nkb - 2);
         last(F1);
-    } else if constexpr (PL == 2) {
+    } else if constexpr (SEL) {
         // row-selective: the split stages first, then the high plane alone
         StageFrags<FT, 1> G0, G1;
         if (nsel > 0) {
@@ -2056,15 +2077,16 @@ __device__ inline void corr2_tile(const CorrJob& C, int I, int J, char* lds, int
 
 // Occupancy: two workgroups of 4 waves per CU for TM = 128, one of 8 for
 // TM = 256 -- two waves per SIMD, so at most 256 VGPRs each.
-template <int P, int TM>
+template <int P, int TM, bool SEL = false>
 __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_kernel(CorrJob C) {
     __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
     __shared__ __attribute__((aligned(16))) int sexp[TM + 2 * kTileN2];
+    __shared__ int sorder[SEL ? kMaxSelBlocks : 1];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int I, J;
     if (C.homo) decode_upper(t, C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
     else decode_full(t, C.tiles_i, C.tiles_j, C.group, I, J);
-    corr2_tile<P, TM>(C, I, J, lds, sexp);
+    corr2_tile<P, TM, SEL>(C, I, J, lds, sexp, sorder);
 }
 
 template <int P, int TM>
@@ -2093,7 +2115,7 @@ __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kerne
         const CorrJob C = jobs[lo];
         int I, J;
         decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
-        corr2_tile<P, TM>(C, I, J, lds, sexp);
+        corr2_tile<P, TM, false>(C, I, J, lds, sexp, nullptr);
     }
 }
 
@@ -2419,6 +2441,17 @@ hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipSt
 #define CORR2_CASES(X) X(P_SPLIT) X(P_BF16) X(P_F16) X(P_SPLIT16)
 
 hipError_t launch_corr(int prec, int fm, int fn, const CorrJob& C, int64_t blocks, hipStream_t s) {
+    // row-selective split: the kernels that read the K-block order
+    if (C.kb_sel && (prec == P_SPLIT || prec == P_SPLIT16) && (fm == 8 || fm == 4) && fn == 4) {
+        if (prec == P_SPLIT) {
+            if (fm == 8) hipLaunchKernelGGL((corr2_kernel<P_SPLIT, 256, true>), dim3((unsigned)blocks), dim3(512), 0, s, C);
+            else hipLaunchKernelGGL((corr2_kernel<P_SPLIT, 128, true>), dim3((unsigned)blocks), dim3(256), 0, s, C);
+        } else {
+            if (fm == 8) hipLaunchKernelGGL((corr2_kernel<P_SPLIT16, 256, true>), dim3((unsigned)blocks), dim3(512), 0, s, C);
+            else hipLaunchKernelGGL((corr2_kernel<P_SPLIT16, 128, true>), dim3((unsigned)blocks), dim3(256), 0, s, C);
+        }
+        return hipGetLastError();
+    }
 #define Y(PP)                                                                                 \
     if (prec == PP && (fm == 8 || fm == 4) && fn == 4) {                                      \
         if (fm == 8) hipLaunchKernelGGL((corr2_kernel<PP, 256>), dim3((unsigned)blocks), dim3(512), 0, s, C); \
