@@ -532,6 +532,9 @@ def batch_workload(B, torch, oracle, synth, dev, otimes):
                 worst[name] = (0.0, k, e_phi, e_psi)
         del o_phi, o_psi
     entries = sum(it.n * (it.n + 1) // 2 for it in items)
+    alg_flops = sum(4.0 * it.m * it.n * (it.n + 1) / 2 for it in items)
+    out_bytes = 8.0 * entries                                    # both FP32 planes
+    in_bytes = sum(8.0 * it.m * it.n for it in items)            # FP64 spectra read once
     otimes.append({"workload": f"batch of {len(items)} sets, upper triangles", "threads": oracle.threads(),
                    "seconds": osecs, "entries_per_s": entries / osecs})
     desc = f"batch of {len(items)} homocorrelations, m in 8..200, n in 256..8192, "
@@ -546,6 +549,20 @@ def batch_workload(B, torch, oracle, synth, dev, otimes):
                            "err_phi": w[2], "err_psi": w[3]},
              "error_measure": "relative Frobenius over all data sets' full matrices; "
                               "worst_set: the largest per-set error"}
+        # the whole batch's roofline (one call): the algorithm's intensity
+        # (4m flops per 8 stored bytes) is above the FP32 ridge (157.3/8 flop/B)
+        # and below the 16-bit one (2500/8): FP32 is bound by its MFMA peak,
+        # the split forms by HBM
+        sec = res[name] * 1e-3
+        if prec == "f32":
+            ach = alg_flops / sec / 1e12
+            r["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f32"],
+                             "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["f32"],
+                             "algorithmic_flops_per_call": alg_flops}
+        else:
+            ach = (out_bytes + in_bytes) / sec / 1e9
+            r["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_GBPS, "unit": "GB/s",
+                             "frac": ach / HBM_GBPS, "algorithmic_bytes_per_call": out_bytes + in_bytes}
         if name == "graph":
             r["sequential_ms_per_call"] = res["sequential"]
             r["graph_speedup"] = res["sequential"] / res["graph"]
