@@ -6,7 +6,7 @@ band workload (128 Lorentzian/Gaussian bands, amplitudes 1e-3..1e2, noise
 1e-4; upper triangle stored, FP32 output): the FFT tables, the radix FFT
 transform with the FP64 centring fused in (m = 256 is a power of two in
 [128, 1024]) writing split-BF16 Fourier operands, and the split-BF16 MFMA
-contraction with its FP64 epilogue.  Inputs are resident in HBM before
+contraction with its epilogue (normalization and unscaling).  Inputs are resident in HBM before
 timing.
 
 Prints ONE JSON line: throughput in correlation entries/s (stored
