@@ -2099,6 +2099,22 @@ __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_kernel(CorrJob C
     corr2_tile<P, TM, SEL>(C, I, J, lds, sexp, sorder);
 }
 
+// Tile of a persistent workgroup's k-th turn (register-direct kernels): the
+// grid takes the tiles in rounds of gridDim.x, and a round's tiles are dealt
+// so that each XCD (the workgroups are dealt to the 8 XCDs in turn) takes a
+// contiguous run of the tile order, whose operand panels its L2 then
+// shares.  Fixed shares instead of an atomic ticket: the tiles are in
+// descending cost order, so the rounds are balanced, and a workgroup's tiles
+// only move forward in the job list.  On the 256-set batch: FP32 18.3 ->
+// 17.9 ms; plain round-robin rounds 18.2 ms.  (The LDS-staged persistent
+// kernel keeps its ticket: fixed shares made the split-BF16 batch 2 % slower,
+// round-robin ones 5 %.)
+__device__ inline int64_t persistent_tile(int64_t k) {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t off = (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+    return k * G + off;
+}
+
 template <int P, int TM>
 __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kernel(const CorrJob* jobs,
                                                                        const int64_t* tile_start,
@@ -2154,24 +2170,17 @@ __global__ __launch_bounds__(256, FM * FN < 16 ? 2 : 1) void corr_persistent_ker
                                                                int* counter) {
     extern __shared__ __attribute__((aligned(16))) char corr_lds[];
     __shared__ __attribute__((aligned(16))) int sexp[32 * FM + 64 * FN];
-    __shared__ int64_t s_t;
-    for (;;) {
-        if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
-        __syncthreads();
-        const int64_t t = uniform64(s_t);
-        __syncthreads();
+    int lo = 0;
+    for (int64_t k = 0;; ++k) {
+        const int64_t t = persistent_tile(k);
         if (t >= total) break;
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tile_start[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
+        while (lo + 1 < count && tile_start[lo + 1] <= t) ++lo;
         const CorrJob C = jobs[lo];
         int I, J;
         decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
         corr_tile<P, FM, FN>(C, I, J, corr_lds, sexp);
     }
+    (void)counter;
 }
 
 // =========================================================================
