@@ -2123,6 +2123,7 @@ __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kerne
     __shared__ __attribute__((aligned(1024))) char lds[corr2_lds_bytes<P, TM>()];
     __shared__ __attribute__((aligned(16))) int sexp[TM + 2 * kTileN2];
     __shared__ int64_t s_t;
+    int lo = 0;
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
         __syncthreads();
@@ -2132,12 +2133,8 @@ __global__ __launch_bounds__(threads2(TM), 256 / TM) void corr2_persistent_kerne
         const int64_t t = uniform64(s_t);
         __syncthreads();
         if (t >= total) break;
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tile_start[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
+        // a workgroup's tickets increase: its job only moves forward
+        while (lo + 1 < count && tile_start[lo + 1] <= t) ++lo;
         const CorrJob C = jobs[lo];
         int I, J;
         decode_upper(t - tile_start[lo], C.tiles_i, C.tiles_j, C.ratio, C.group, I, J);
