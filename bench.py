@@ -5,9 +5,10 @@ One step = one corr2d_homo call through the C ABI on the m=256 x n=16384
 band workload (128 Lorentzian/Gaussian bands, amplitudes 1e-3..1e2, noise
 1e-4; upper triangle stored, FP32 output): the FFT tables, the radix FFT
 transform with the FP64 centring fused in (m = 256 is a power of two in
-[128, 1024]) writing split-BF16 Fourier operands, and the split-BF16 MFMA
-contraction with its epilogue (normalization and unscaling).  Inputs are resident in HBM before
-timing.
+[128, 1024]) writing split-BF16 operands in the default time basis (the
+centred spectra and Noda's N Yc as an FFT correlation), and the split-BF16
+MFMA contraction with its epilogue (normalization and unscaling).  Inputs
+are resident in HBM before timing.
 
 Prints ONE JSON line: throughput in correlation entries/s (stored
 (Phi, Psi) pairs), the roofline of the contraction kernel (timed alone with
@@ -231,7 +232,8 @@ def run_variant(B, torch, y, n, m, prec, basis, steps, warmup, ev, ref,
               "split_f16": 4}[prec]
     kernel_bytes = 2 * entries * esz + 2 * n * info.k_pad * planes
     res = {
-        "prec": prec, "basis": basis, "scale_alpha": alpha, "layout": layout,
+        "prec": prec, "basis": {v: k for k, v in B.BASIS.items()}[plan.info.basis],
+        "scale_alpha": alpha, "layout": layout,
         "ms_per_step": wall * 1e3 / steps,
         "entries_per_s": entries / (wall / steps),
         "kernel_ms": kernel_ms,
@@ -687,17 +689,19 @@ def main():
     ref = (o_phi, o_psi, diag, a2p)
 
     layout = args.layout
-    main_res = run_variant(B, torch, y, n, m, "split_bf16", "fourier", args.steps, args.warmup,
+    main_res = run_variant(B, torch, y, n, m, "split_bf16", "auto", args.steps, args.warmup,
                            ev, ref, layout=layout)
     variants = []
     if not args.no_variants:
         vs = args.variant_steps
         # the headline form in the other upper-triangle layout
         other = "upper_packed" if layout == "upper_aligned" else "upper_aligned"
-        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, ref,
+        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "auto", vs, 1, ev, ref,
                                     layout=other))
-        for prec, basis in (("split_f16", "fourier"), ("f32", "fourier"), ("bf16", "fourier"),
-                            ("bf16", "time"), ("f64", "fourier")):
+        # the headline form in the Fourier basis (the default is the time
+        # basis), and the other formats
+        for prec, basis in (("split_bf16", "fourier"), ("split_f16", "auto"), ("f32", "auto"),
+                            ("bf16", "fourier"), ("bf16", "auto"), ("f64", "auto")):
             variants.append(run_variant(B, torch, y, n, m, prec, basis, vs, 1, ev, ref,
                                         layout=layout))
         # the row-selective split (low plane on the high-energy Fourier rows
@@ -716,7 +720,7 @@ def main():
         del rows, cols
         pref = (o_phi * w, o_psi * w, diag, a2p)
         del w
-        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "fourier", vs, 1, ev, pref,
+        variants.append(run_variant(B, torch, y, n, m, "split_bf16", "auto", vs, 1, ev, pref,
                                     alpha=0.5, layout=layout))
         del pref
     del ref, o_phi, o_psi, a2p
@@ -752,7 +756,7 @@ def main():
         "dtype": "split-bf16",
         "data": "synthetic",
         "config": {"workload": f"homocorrelation m={m} n={n} band spectra, upper triangle "
-                               f"({LAYOUT_TEXT[layout]}), FP32 output, Fourier basis, Noda kernel",
+                               f"({LAYOUT_TEXT[layout]}), FP32 output, time basis, Noda kernel",
                    "m": m, "n": n, "layout": layout, "prec": "split_bf16",
                    "entries_per_step": n * (n + 1) // 2},
         # The algorithm's intensity (4m flops per 8 written bytes, plus the

@@ -243,15 +243,20 @@ corr2d_status check_common(const corr2d_desc* d) {
     return CORR2D_OK;
 }
 
-// CORR2D_BASIS_AUTO: the time basis for plain BF16, whose single rounding
-// of each operand then spreads over all m products of a sum instead of
-// concentrating in the few Fourier rows that carry the bands (a measured
-// 7x smaller error on band spectra); the Fourier basis otherwise, and
-// wherever the kernel needs it (the R bin list).
+// CORR2D_BASIS_AUTO: the time basis, where the operands' rounding errors
+// spread over all m products of a sum instead of concentrating in the few
+// Fourier rows that carry a band spectrum's energy.  Measured on the band
+// workloads (relative Frobenius error over the full matrices, Fourier ->
+// time): split-BF16 4.7e-6 -> 6.7e-7 at m = 256 and 5.4e-5 -> 9.1e-6 on the
+// worst of the 256 batched data sets, FP16 3.1e-4 -> 4.4e-5, FP8 4.0e-2 ->
+// 7.1e-3, plain BF16 2.5e-3 -> 3.5e-4, FP32 4.4e-7 -> 2.7e-7, FP64 equal;
+// the contraction costs the same.  The Fourier basis where the method
+// needs it: the R bin list, and the row-selective split (it picks Fourier
+// rows).
 int resolve_basis(const corr2d_desc* d) {
     if (d->basis != CORR2D_BASIS_AUTO) return d->basis;
-    if (d->prec == CORR2D_PREC_BF16 && d->hilbert != CORR2D_HILBERT_R_COMPAT) return CORR2D_BASIS_TIME;
-    return CORR2D_BASIS_FOURIER;
+    if (d->hilbert == CORR2D_HILBERT_R_COMPAT || (d->flags & CORR2D_FLAG_SPLIT_ROWS)) return CORR2D_BASIS_FOURIER;
+    return CORR2D_BASIS_TIME;
 }
 
 double norm_cF(const corr2d_desc* d, int64_t m) {

@@ -95,16 +95,18 @@ def test_defaults():
     assert B.corr2d_version().startswith("corr2d")
 
 
-@pytest.mark.parametrize("prec,hilbert,expect", [
-    ("bf16", "noda", "time"), ("bf16", "circular", "time"), ("bf16", "r_compat", "fourier"),
-    ("split_bf16", "noda", "fourier"), ("split_f16", "noda", "fourier"), ("f32", "noda", "fourier"),
-    ("f64", "noda", "fourier"), ("f16", "noda", "fourier"), ("fp8_e4m3", "noda", "fourier"),
+@pytest.mark.parametrize("prec,hilbert,flags,expect", [
+    ("bf16", "noda", 0, "time"), ("bf16", "circular", 0, "time"), ("bf16", "r_compat", 0, "fourier"),
+    ("split_bf16", "noda", 0, "time"), ("split_f16", "noda", 0, "time"), ("f32", "noda", 0, "time"),
+    ("f64", "noda", 0, "time"), ("f16", "noda", 0, "time"), ("fp8_e4m3", "noda", 0, "time"),
+    ("f32", "r_compat", 0, "fourier"), ("split_bf16", "noda", B.FLAG_SPLIT_ROWS, "fourier"),
+    ("split_f16", "circular", B.FLAG_SPLIT_ROWS, "fourier"),
 ])
-def test_auto_basis_resolution(prec, hilbert, expect):
-    """The default basis resolves to the time basis for plain BF16 (except
-    with the R bin list, which needs the Fourier basis) and to the Fourier
-    basis for every other format; plan info reports the basis in use."""
-    p = B.Plan(m=64, n1=300, n2=0, prec=prec, hilbert=hilbert)
+def test_auto_basis_resolution(prec, hilbert, flags, expect):
+    """The default basis resolves to the time basis, except with the R bin
+    list and the row-selective split, which need the Fourier basis; plan
+    info reports the basis in use."""
+    p = B.Plan(m=64, n1=300, n2=0, prec=prec, hilbert=hilbert, flags=flags)
     assert p.info.basis == B.BASIS[expect]
     q = B.Plan(m=64, n1=300, n2=0, prec=prec, hilbert=hilbert, basis="fourier")
     assert q.info.basis == B.BASIS["fourier"]
@@ -228,13 +230,18 @@ def test_plan_info():
     t = 16384 // info.tile_m
     assert info.tiles == sum(2 * t - 2 * i for i in range(t)) == t * (t + 1)
     B.corr2d_plan_destroy(h)
-    d = B.corr2d_desc_init(m=256, n1=16384, prec="split_bf16", out_layout="upper_packed", tile=3)
+    d = B.corr2d_desc_init(m=256, n1=16384, prec="split_bf16", out_layout="upper_packed", tile=3,
+                           basis="fourier")
     _, h = B.corr2d_plan(d)
     info = B.corr2d_plan_get_info(h)
     assert (info.tile_m, info.tile_n) == (128, 128)
     t = 16384 // 128
     assert info.tiles == t * (t + 1) // 2
-    assert info.c == pytest.approx(1.0 / (256 * 255))
+    assert info.c == pytest.approx(1.0 / (256 * 255))   # Fourier operands carry m (Parseval)
+    B.corr2d_plan_destroy(h)
+    d = B.corr2d_desc_init(m=256, n1=16384, prec="split_bf16", out_layout="upper_packed")
+    _, h = B.corr2d_plan(d)
+    assert B.corr2d_plan_get_info(h).c == pytest.approx(1.0 / 255)   # default: time basis
     B.corr2d_plan_destroy(h)
     d = B.corr2d_desc_init(m=10, n1=7, prec="f64", norm_mode="paper", basis="time")
     _, h = B.corr2d_plan(d)
@@ -273,13 +280,14 @@ def test_plan_info_reference_offsets(kw):
     (dict(m=256, prec="f64"), 1), (dict(m=100, prec="f64"), 0), (dict(m=256, basis="time"), 1),
     (dict(m=256, basis="time", hilbert="circular"), 0),
     (dict(m=256, flags=B.FLAG_TRANSFORM_MATMUL), 0),
-    (dict(m=256, hilbert="circular"), 1), (dict(m=256, hilbert="r_compat"), 1),
+    (dict(m=256, hilbert="circular", basis="fourier"), 1), (dict(m=256, hilbert="r_compat"), 1),
+    (dict(m=256, hilbert="circular"), 0),   # default: time basis, table product for this kernel
     (dict(m=128, n2=40), 1), (dict(m=256, prec="fp8_e4m3"), 1),
 ])
 def test_transform_selection(kw, fft):
     """The radix FFT transform serves power-of-two 128 <= m <= 1024 (Fourier
-    basis; time basis with Noda's kernel), unless the flag asks for the
-    product."""
+    basis; time basis with Noda's kernel, the default), unless the flag asks
+    for the product."""
     base = dict(n1=300)
     base.update(kw)
     _, h = B.corr2d_plan(B.corr2d_desc_init(**base))

@@ -687,14 +687,16 @@ def _transform(plan):
     return B.corr2d_plan_get_info(plan.handle).transform
 
 
+@pytest.mark.parametrize("basis", ["fourier", "time"])
 @pytest.mark.parametrize("prec", FFT_PRECS)
 @pytest.mark.parametrize("m,n", [(128, 300), (256, 129), (512, 70), (1024, 33)])
-def test_fft_transform_parity(gpu, prec, m, n):
+def test_fft_transform_parity(gpu, prec, m, n, basis):
     """Every FFT length (L = 256 .. 2048: radix 8 passes with a radix-4 or
-    radix-2 last pass) and operand format; ragged n leaves padded points."""
+    radix-2 last pass), operand format and basis; ragged n leaves padded
+    points."""
     S = _rand(m, n, 31 * m + n)
     phi_o, psi_o = oracle.corr2d(S)
-    phi, psi, plan = _homo(S, gpu, prec=prec)
+    phi, psi, plan = _homo(S, gpu, prec=prec, basis=basis)
     assert _transform(plan) == 1
     check_homo_structure(phi, psi)
     assert rel_fro(phi, phi_o) <= TOL[prec]
@@ -709,8 +711,8 @@ def test_fft_transform_modes_and_matmul_flag(gpu, prec, hilbert, norm):
     m, n = 256, 200
     S = _rand(m, n, 77)
     phi_o, psi_o = oracle.corr2d(S, hilbert=hilbert, norm=norm)
-    a = _homo(S, gpu, prec=prec, hilbert=hilbert, norm=norm)
-    b = _homo(S, gpu, prec=prec, hilbert=hilbert, norm=norm, flags=B.FLAG_TRANSFORM_MATMUL)
+    a = _homo(S, gpu, prec=prec, hilbert=hilbert, norm=norm, basis="fourier")
+    b = _homo(S, gpu, prec=prec, hilbert=hilbert, norm=norm, basis="fourier", flags=B.FLAG_TRANSFORM_MATMUL)
     assert _transform(a[2]) == 1 and _transform(b[2]) == 0
     for phi, psi, _ in (a, b):
         check_homo_structure(phi, psi)

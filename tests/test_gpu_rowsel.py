@@ -51,7 +51,7 @@ def test_tiny_target_is_the_full_split(gpu, prec, m, n):
     nsel = _check_selection(B.selection(ws, plan), plan.info.k_pad)
     assert nsel == plan.info.k_pad // 16
     assert B.selection(ws, plan)[1] == list(range(plan.info.k_pad // 16))
-    fphi, fpsi, _, _ = B.homo(y, prec=prec)
+    fphi, fpsi, _, _ = B.homo(y, prec=prec, basis="fourier")
     assert np.array_equal(_np(phi), _np(fphi)) and np.array_equal(_np(psi), _np(fpsi))
 
 

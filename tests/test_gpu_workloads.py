@@ -45,6 +45,9 @@ def large():
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec,basis,tol,flags,layout", [
+    ("split_bf16", "auto", TOL["split_bf16"], 0, "upper_aligned"),
+    ("split_f16", "auto", TOL["split_f16"], 0, "upper_aligned"),
+    ("f32", "auto", TOL["f32"], 0, "upper_aligned"),
     ("split_bf16", "fourier", TOL["split_bf16"], 0, "upper_aligned"),
     ("split_bf16", "fourier", TOL["split_bf16"], B.FLAG_TRANSFORM_MATMUL, "upper_packed"),
     ("f32", "fourier", TOL["f32"], 0, "upper_aligned"),
@@ -56,7 +59,8 @@ def large():
 ])
 def test_large_homo_full(gpu, large, prec, basis, tol, flags, layout):
     """m=256, n=16384 band workload, upper triangle stored (the bench's
-    launch), through the radix FFT transform (the default at this m) and,
+    launch: the default, time basis), in both bases, through the radix FFT
+    transform (the default at this m) and,
     forced by the flag, the table product: every entry of the full Phi and
     Psi against the oracle (relative Frobenius error over the full matrix,
     and each entry within its own bound, gpu_helpers.ELEMENT_TAU).  Plain
@@ -244,11 +248,12 @@ def test_batched_full_size_every_set(gpu):
     256..8192; the bench's launch): the graph-replayed persistent launch in
     FP32, split-FP16 and split-BF16, every data set's full Phi and Psi
     against the oracle, every entry within its own bound; FP32 sequential
-    launches give the same bits.  FP32 and split-FP16 hold 1e-5 (relative
-    Frobenius over each full matrix) on every data set.  Split-BF16 holds it
-    over the whole batch; on a data set whose Psi cancels strongly (four
-    bands, measured 5.4e-5 there) its 8-bit halves cannot, which is what
-    split-FP16's 11-bit halves fix (1e-6 on that set)."""
+    launches give the same bits.  FP32, split-FP16 and split-BF16 hold 1e-5
+    (relative Frobenius over each full matrix) on every data set in the
+    default time basis (split-BF16's worst, a data set whose Psi cancels
+    about twentyfold, measures 9.1e-6; in the Fourier basis, where the
+    rounding errors of its 8-bit halves pile up in the few rows that carry
+    the bands, 5.4e-5)."""
     import time as _time
     import torch
     items = synth.batch_spec()
@@ -281,8 +286,7 @@ def test_batched_full_size_every_set(gpu):
                 total[name][2 * q + 1] += fe.den[q]
             if name not in worst or max(e[:2]) > max(worst[name][1][:2]):
                 worst[name] = (k, e)
-            if prec != "split_bf16":
-                assert e[0] <= TOL[prec] and e[1] <= TOL[prec], (name, k, it.m, it.n, e)
+            assert e[0] <= TOL[prec] and e[1] <= TOL[prec], (name, k, it.m, it.n, e)
             assert e[2] <= 1.0, (name, k, it.m, it.n, e)
         del blocks
         if k % 32 == 31:
