@@ -785,13 +785,13 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
 
 corr2d_status corr2d_plan_destroy(corr2d_plan_t p) {
     if (!p) return ok();
-    if (p->have_graph && p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->have_graph && p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->blob_done) {
-        if (p->blob_recorded) hipEventSynchronize(p->blob_done);
-        hipEventDestroy(p->blob_done);
+        if (p->blob_recorded) (void)hipEventSynchronize(p->blob_done);
+        (void)hipEventDestroy(p->blob_done);
     }
-    if (p->host_blob) hipHostFree(p->host_blob);
-    if (p->iw_blob) hipHostFree(p->iw_blob);
+    if (p->host_blob) (void)hipHostFree(p->host_blob);
+    if (p->iw_blob) (void)hipHostFree(p->iw_blob);
     delete p;
     return ok();
 }
@@ -935,10 +935,10 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g1, p->s1, ws, phi, psi, true, p->c, p->tile,
                               p->d.ld_out, p->d.out_layout);
     if (p->rowsel) C.kb_sel = at<int32_t>(ws, p->sel_off);
-    if (g_ev_before) hipEventRecord(g_ev_before, s);
+    if (g_ev_before) (void)hipEventRecord(g_ev_before, s);
     e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
     if (e != hipSuccess) return device_fail(e, "correlation launch");
-    if (g_ev_after) hipEventRecord(g_ev_after, s);
+    if (g_ev_after) (void)hipEventRecord(g_ev_after, s);
     return ok();
 }
 
@@ -1001,10 +1001,10 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     CorrJob C = make_corr_job(p, p->g1, p->s1, p->g2, p->s2, ws, phi, psi, false, p->c, p->tile,
                               p->d.ld_out, CORR2D_LAYOUT_FULL);
     if (p->rowsel) C.kb_sel = at<int32_t>(ws, p->sel_off);
-    if (g_ev_before) hipEventRecord(g_ev_before, s);
+    if (g_ev_before) (void)hipEventRecord(g_ev_before, s);
     e = launch_corr(p->d.prec, p->tile.fm, p->tile.fn, C, C.ntiles, s);
     if (e != hipSuccess) return device_fail(e, "correlation launch");
-    if (g_ev_after) hipEventRecord(g_ev_after, s);
+    if (g_ev_after) (void)hipEventRecord(g_ev_after, s);
     return ok();
 }
 
@@ -1127,7 +1127,7 @@ corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
     if (e != hipSuccess) return device_fail(e, "transform launch");
 
     int dev_id = 0, cus = 0;
-    hipGetDevice(&dev_id);
+    (void)hipGetDevice(&dev_id);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess || cus <= 0)
         cus = 256;
     // one persistent launch per tile shape, each with its own ticket counter
@@ -1233,7 +1233,7 @@ extern "C" corr2d_status corr2d_batched(corr2d_plan_t p, const void* y_base, voi
         p->blob_valid = true;
         p->blob_key = key;
         if (p->have_graph) {
-            hipGraphExecDestroy(p->gexec);
+            (void)hipGraphExecDestroy(p->gexec);
             p->gexec = nullptr;
             p->have_graph = false;
         }
@@ -1255,20 +1255,20 @@ extern "C" corr2d_status corr2d_batched(corr2d_plan_t p, const void* y_base, voi
         }
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
-            if (own) hipStreamDestroy(cs);
+            if (own) (void)hipStreamDestroy(cs);
             return device_fail(e, "begin capture");
         }
         corr2d_status est = enqueue_batched(p, ws, cs);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
-        if (own) hipStreamDestroy(cs);
+        if (own) (void)hipStreamDestroy(cs);
         if (est != CORR2D_OK) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return est;
         }
         if (e != hipSuccess) return device_fail(e, "end capture");
         e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return device_fail(e, "graph instantiate");
         p->have_graph = true;
     }
