@@ -70,7 +70,7 @@ def write_table(lines, path, header):
             f.write(ln + "\n")
 
 
-def time_tile(B, torch, prec, m, n, tile, ev, reps=5):
+def time_tile(B, torch, prec, m, n, tile, ev, reps=11):
     """Median contraction-kernel time (ms) of one homocorrelation plan (row-aligned
     upper triangle, the benchmark's layout)."""
     import numpy as np
