@@ -280,8 +280,9 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d);
  * plan runs all sets through one chain of launches instead.  The common
  * descriptor supplies precision, basis, kernel, norm, layout, dtypes and
  * flags (its m, n1, n2, strides are ignored).  Each set's outputs have the
- * common layout with row stride n.  Errors as corr2d_plan, per item;
- * EUNSUPPORTED for interpolation.                                           */
+ * common layout with row stride n.  All sets use one output tile shape: the
+ * descriptor's tile, else the tuned shape of the set with the largest
+ * m n^2.  Errors as corr2d_plan, per item; EUNSUPPORTED for interpolation. */
 corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
                                   const corr2d_item* items, int64_t count);
 
@@ -338,7 +339,7 @@ corr2d_status corr2d_hetero(corr2d_plan_t plan, const void* y1, const double* re
 /* Batched homocorrelation: corr2d(Mat1) (Sec. 3) of every data set of the
  * plan.  y_base, phi_base, psi_base: device; each set at its item offsets.
  * With neither SEQUENTIAL nor NO_GRAPH the whole batch (prep and one
- * persistent contraction launch per tile shape) is replayed from a hipGraph
+ * persistent contraction launch) is replayed from a hipGraph
  * the plan captures on first use for these pointers and stream; the job
  * arrays are uploaded from a pinned host buffer that the plan allocates on
  * its first call.  A call with other pointers or another stream than the
