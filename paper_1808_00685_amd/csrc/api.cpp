@@ -131,6 +131,9 @@ struct corr2d_plan_s {
     // single / hetero
     Geo g1, g2;
     bool fft = false;         // radix FFT transform (else the table product)
+    // table product with the centring fused into it (not FP64, kt small enough
+    // for the centred columns to stay in LDS): no separate centring launch
+    bool fused_center = false;
     // row-selective split: energy partials per operand, the selection record
     bool rowsel = false;
     double fmax = 0.0;
@@ -606,6 +609,14 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     const bool t64 = d->prec == CORR2D_PREC_F64;
     p->g1 = geometry(d->m, d->n1, d->prec);
     p->fft = use_fft(&p->d, d->m);
+    // a single call fuses the centring only when the fused launch fills the
+    // GPU: it has one workgroup per 64 spectral points (and 256 transform
+    // rows), where the separate centring has one per 32; at m = 64, n = 4096
+    // (64 workgroups) fusing cost 3 us per call
+    const int fused_blocks = transform_blocks(p->g1, d->prec) +
+                             (hetero ? transform_blocks(geometry(d->m, d->n2, d->prec), d->prec) : 0);
+    p->fused_center = !p->fft && d->prec != CORR2D_PREC_F64 && p->g1.kt <= kFusedTransformMaxK &&
+                      fused_blocks >= kFusedMinBlocks;
     size_t off = 0;
     p->table_off = off;
     off = align256(off + table_bytes(p->g1, t64));
@@ -667,7 +678,8 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
                      "transform=%s prep_launches=%d per_band_scale=%d row_select=%d workspace=%zu B tune: %s\n",
                      prec_name(d->prec), (long long)d->m, (long long)d->n1, (long long)d->n2, d->out_layout,
                      p->tile.id, 32 * p->tile.fm, 32 * p->tile.fn, (long long)p->ntiles,
-                     p->fft ? "radix FFT" : "DFT table product", p->fft ? 2 : (merged_prep(p) ? 2 : (needs_qn(p) ? 4 : 3)),
+                     p->fft ? "radix FFT" : (p->fused_center ? "DFT table product, centring fused" : "DFT table product"),
+                     p->fft ? 2 : (merged_prep(p) ? 2 : (needs_qn(p) ? 4 : 3) - (p->fused_center ? 1 : 0)),
                      (int)p->scale, (int)p->rowsel, p->ws_bytes, tune_source());
     *out = p;
     return ok();
@@ -748,6 +760,8 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
                                  : I.it.n * I.it.n;
         p->out_elements = std::max(p->out_elements, I.it.out_offset + outn);
     }
+    p->fused_center = common->prec != CORR2D_PREC_F64;
+    for (const auto& I : p->items) p->fused_center = p->fused_center && I.g.kt <= kFusedTransformMaxK;
     // grouped by tile shape, each group in descending cost order (longest
     // processing time first)
     p->order.resize(count);
@@ -931,10 +945,11 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
     if (p->interp) ps.j[0].in_f64 = 1;
     ps.count = 1;
     ps.blocks0 = center_blocks(p->g1);
-    // the FFT transform centres the spectra itself
+    // the FFT transform, and the fused table product, centre the spectra themselves
     if (merged_prep(p))
-        e = launch_prep(ts, ts.blocks0, needs_qn(p) ? qn_blocks(p->g1.m) : 0, p->g1.m, ps, ps.blocks0, s);
-    else if (!p->fft)
+        e = launch_prep(ts, ts.blocks0, needs_qn(p) ? qn_blocks(p->g1.m) : 0, p->g1.m, ps,
+                        p->fused_center ? 0 : ps.blocks0, s);
+    else if (!p->fft && !p->fused_center)
         e = launch_center(ps, ps.blocks0, s);
     if (e != hipSuccess) return device_fail(e, "center launch");
     if (p->fft) {
@@ -942,7 +957,8 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
         e = launch_fft_transform(p->d.prec, fft_log2(p->g1.m), ps, ps.blocks0, s);
     } else {
         ps.blocks0 = transform_blocks(p->g1, p->d.prec);
-        e = launch_transform(p->d.prec, ps, ps.blocks0, s);
+        e = p->fused_center ? launch_center_transform(p->d.prec, ps, ps.blocks0, s)
+                            : launch_transform(p->d.prec, ps, ps.blocks0, s);
     }
     if (e != hipSuccess) return device_fail(e, "transform launch");
     if (p->rowsel && (e = launch_selection(p, ws, s)) != hipSuccess) return device_fail(e, "row selection launch");
@@ -999,8 +1015,8 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
     ps.blocks0 = center_blocks(p->g1);
     if (merged_prep(p))
         e = launch_prep(ts, ts.blocks0, needs_qn(p) ? qn_blocks(p->g1.m) : 0, p->g1.m, ps,
-                        ps.blocks0 + center_blocks(p->g2), s);
-    else if (!p->fft)
+                        p->fused_center ? 0 : ps.blocks0 + center_blocks(p->g2), s);
+    else if (!p->fft && !p->fused_center)
         e = launch_center(ps, ps.blocks0 + center_blocks(p->g2), s);
     if (e != hipSuccess) return device_fail(e, "center launch");
     if (p->fft) {
@@ -1008,7 +1024,8 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
         e = launch_fft_transform(p->d.prec, fft_log2(p->g1.m), ps, ps.blocks0 + fft_blocks(p->g2), s);
     } else {
         ps.blocks0 = transform_blocks(p->g1, p->d.prec);
-        e = launch_transform(p->d.prec, ps, ps.blocks0 + transform_blocks(p->g2, p->d.prec), s);
+        const int nb = ps.blocks0 + transform_blocks(p->g2, p->d.prec);
+        e = p->fused_center ? launch_center_transform(p->d.prec, ps, nb, s) : launch_transform(p->d.prec, ps, nb, s);
     }
     if (e != hipSuccess) return device_fail(e, "transform launch");
     if (p->rowsel && (e = launch_selection(p, ws, s)) != hipSuccess) return device_fail(e, "row selection launch");
@@ -1134,11 +1151,14 @@ corr2d_status enqueue_batched(corr2d_plan_s* p, void* ws, hipStream_t s) {
     PrepSrcArray pa{};
     pa.jobs = (const PrepJob*)(dev + L.prep);
     pa.count = (int32_t)count;
-    pa.start = (const int32_t*)(dev + L.cstart);
-    e = launch_center(pa, ((const int32_t*)(h + L.cstart))[count], s);
-    if (e != hipSuccess) return device_fail(e, "center launch");
+    if (!p->fused_center) {
+        pa.start = (const int32_t*)(dev + L.cstart);
+        e = launch_center(pa, ((const int32_t*)(h + L.cstart))[count], s);
+        if (e != hipSuccess) return device_fail(e, "center launch");
+    }
     pa.start = (const int32_t*)(dev + L.xstart);
-    e = launch_transform(p->d.prec, pa, ((const int32_t*)(h + L.xstart))[count], s);
+    const int xb = ((const int32_t*)(h + L.xstart))[count];
+    e = p->fused_center ? launch_center_transform(p->d.prec, pa, xb, s) : launch_transform(p->d.prec, pa, xb, s);
     if (e != hipSuccess) return device_fail(e, "transform launch");
 
     int dev_id = 0, cus = 0;
@@ -1179,10 +1199,11 @@ corr2d_status enqueue_sequential(corr2d_plan_s* p, const void* y_base, void* phi
                                 nullptr, ws, I.table_off);
         ps.count = 1;
         ps.blocks0 = center_blocks(I.g);
-        e = launch_center(ps, ps.blocks0, s);
+        if (!p->fused_center) e = launch_center(ps, ps.blocks0, s);
         if (e != hipSuccess) return device_fail(e, "center launch");
         ps.blocks0 = transform_blocks(I.g, p->d.prec);
-        e = launch_transform(p->d.prec, ps, ps.blocks0, s);
+        e = p->fused_center ? launch_center_transform(p->d.prec, ps, ps.blocks0, s)
+                            : launch_transform(p->d.prec, ps, ps.blocks0, s);
         if (e != hipSuccess) return device_fail(e, "transform launch");
         CorrJob C = make_corr_job(p, I.g, I.s, I.g, I.s, ws, (char*)phi_base + I.it.out_offset * osz,
                                   (char*)psi_base + I.it.out_offset * osz, true, I.c, I.tile, I.it.n,

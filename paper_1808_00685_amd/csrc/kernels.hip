@@ -15,6 +15,11 @@
 //                     for the reduced formats); the epilogue scales, rounds
 //                     (RNE) and packs the contraction operands, zero padded
 //                     (panel-blocked for the 16-bit formats).
+//   center_transform32_kernel
+//                     the centring and transform32_kernel in one kernel for
+//                     m up to 256 (all formats but FP64): each workgroup
+//                     centres its 64 spectral points into LDS and multiplies
+//                     them by the tables there, no centred spectra in HBM.
 //   fft_tables_kernel, fft_transform_kernel
 //                     for power-of-two m in [128, 1024] (FP64 for the FP64
 //                     path, else FP32) in place of the three kernels above: twiddles and the
@@ -695,6 +700,152 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
     for (int b = 0; b < 4; ++b) {
         // rows r0 + 16 b .. + 15 are all A rows or all B rows (K is a
         // multiple of 16); this lane holds rows rb .. rb + 3
+        const int64_t rb0 = r0 + b * 16;
+        if (rb0 >= 2 * (int64_t)J.kp) continue;
+        const bool isB = rb0 >= J.kp;
+        if (isB && !J.need_b) continue;
+        const int64_t k = (isB ? rb0 - J.kp : rb0) + kg * 4;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int il = a * 16 + row16;
+            const int64_t i = i0 + il;
+            const float sc = s_scale[isB ? 1 : 0][il];
+            const float x[4] = {acc[a][b][0] * sc, acc[a][b][1] * sc, acc[a][b][2] * sc, acc[a][b][3] * sc};
+            const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
+            store_operand4<P>(isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx, x);
+        }
+    }
+}
+
+// Centring fused into the FP32 transform GEMM, for short spectra (kt <=
+// kFusedTransformMaxK): each workgroup centres its own 64 spectral points
+// (the mean over the m perturbation steps in FP64, or the given reference,
+// Sec. 2 Eqs. (dynspec), (ref)), applies
+// the result scaling sigma^-alpha, takes each column's norm for the per-band
+// scales, and keeps the centred columns in LDS as the GEMM's B operand, so
+// the centred spectra never go through HBM.  The arithmetic per value is the
+// separate centring kernel's (FP64 difference and scaling, one rounding to
+// FP32); only the order of the FP64 column sums differs.  Workgroups of the
+// same points and another row tile repeat the centring; the first row tile
+// writes the reference, the scales and nothing else of it.
+template <int P, class Src>
+__global__ __launch_bounds__(256) void center_transform32_kernel(Src src) {
+    constexpr int YP = kFusedTransformMaxK + 4;   // LDS row pitch of a centred column (floats)
+    __shared__ __attribute__((aligned(16))) float ytile[64 * YP];
+    __shared__ double red[4][64];
+    __shared__ float s_scale[2][64];
+    int lb;
+    const PrepJob J = src.get(blockIdx.x, lb);
+    const int rtiles = (J.rows_pad + kT32Cols - 1) / kT32Cols;
+    const int bi = lb / rtiles, br = lb % rtiles;
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)bi * 64;
+
+    // centring: thread (g, c) takes rows g, g + 4, ... of column i0 + c, all
+    // loaded at once into registers (the LDS tile already limits the kernel
+    // to two workgroups per CU, so the registers are free)
+    {
+        constexpr int NV = kFusedTransformMaxK / 4;
+        const int c = tid & 63, g = tid >> 6;
+        const int64_t col = i0 + c;
+        const bool valid = col < J.n;
+        double vals[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int j = g + 4 * k;
+            vals[k] = (valid && j < J.m) ? load_in(J, j, col) : 0.0;
+        }
+        double mean = 0.0;
+        if (J.ref) {
+            mean = valid ? J.ref[col] : 0.0;
+        } else {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < NV; k += 2) {
+                s0 += vals[k];
+                s1 += vals[k + 1];
+            }
+            red[g][c] = s0 + s1;
+            __syncthreads();
+            mean = (red[0][c] + red[1][c] + red[2][c] + red[3][c]) / (double)J.m;
+            __syncthreads();
+        }
+        double gsc = 1.0;
+        if (J.alpha != 0.0) {
+            double q0 = 0.0;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const double d = vals[k] - mean;
+                if (valid && g + 4 * k < J.m) q0 += d * d;
+            }
+            red[g][c] = q0;
+            __syncthreads();
+            const double sd = sqrt((red[0][c] + red[1][c] + red[2][c] + red[3][c]) / (double)(J.m - 1));
+            if (sd > 0.0) gsc = pow(sd, -J.alpha);
+            __syncthreads();
+        }
+        double nrm = 0.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int j = g + 4 * k;
+            const double v = (valid && j < J.m) ? (vals[k] - mean) * gsc : 0.0;
+            nrm += v * v;
+            if (j < J.kt) ytile[c * YP + j] = (float)v;
+        }
+        red[g][c] = nrm;
+        __syncthreads();
+        if (g == 0) {
+            const double r = sqrt(red[0][c] + red[1][c] + red[2][c] + red[3][c]);
+            float sa = 1.0f, sb = 1.0f;
+            if (J.scale) {
+                sa = pow2_scale(J.qhalf, J.boundA * r);
+                sb = pow2_scale(J.qhalf, J.boundB * r);
+            }
+            s_scale[0][c] = J.sA ? sa : 0.0f;
+            s_scale[1][c] = J.sB ? sb : 0.0f;
+            if (br == 0) {
+                if (valid && J.ref_out) J.ref_out[col] = mean;
+                if (J.sA) J.sA[col] = sa;
+                if (J.sB) J.sB[col] = sb;
+            }
+        }
+        __syncthreads();
+    }
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int row16 = lane & 15, kg = lane >> 4;
+    const int64_t r0 = (int64_t)br * kT32Cols + wave * 64;
+    if (r0 >= J.rows_pad) return;   // no barrier follows
+    const float* T = (const float*)J.table;
+    const float* yrow[4];
+    const float* trow[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        yrow[a] = ytile + (a * 16 + row16) * YP + kg * 4;
+        trow[a] = T + (r0 + a * 16 + row16) * J.kt + kg * 4;
+    }
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < J.kt; k0 += 16) {
+        f4 fa[4], fb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            fa[a] = *(const f4*)(yrow[a] + k0);
+            fb[a] = *(const f4*)(trow[a] + k0);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b][s], fa[a][s], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
         const int64_t rb0 = r0 + b * 16;
         if (rb0 >= 2 * (int64_t)J.kp) continue;
         const bool isB = rb0 >= J.kp;
@@ -2415,6 +2566,25 @@ static hipError_t launch_transform_t(int prec, const Src& src, int blocks, hipSt
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+template <class Src>
+static hipError_t launch_center_transform_t(int prec, const Src& src, int blocks, hipStream_t s) {
+    switch (prec) {
+    case P_F32: hipLaunchKernelGGL((center_transform32_kernel<P_F32, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_SPLIT: hipLaunchKernelGGL((center_transform32_kernel<P_SPLIT, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_BF16: hipLaunchKernelGGL((center_transform32_kernel<P_BF16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_F16: hipLaunchKernelGGL((center_transform32_kernel<P_F16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_SPLIT16: hipLaunchKernelGGL((center_transform32_kernel<P_SPLIT16, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    case P_FP8: hipLaunchKernelGGL((center_transform32_kernel<P_FP8, Src>), dim3(blocks), dim3(256), 0, s, src); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_center_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s) {
+    return launch_center_transform_t(prec, src, blocks, s);
+}
+hipError_t launch_center_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s) {
+    return launch_center_transform_t(prec, src, blocks, s);
 }
 hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s) {
     return launch_transform_t(prec, src, blocks, s);

@@ -96,6 +96,13 @@ constexpr int64_t kPrepMergeMaxM = 1024;
 hipError_t launch_center(const PrepSrcArray& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s);
 hipError_t launch_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s);
+// Centring fused into the FP32 transform GEMM (not FP64), for kt <=
+// kFusedTransformMaxK; the same workgroups as launch_transform.
+hipError_t launch_center_transform(int prec, const PrepSrcInline& src, int blocks, hipStream_t s);
+hipError_t launch_center_transform(int prec, const PrepSrcArray& src, int blocks, hipStream_t s);
+constexpr int kFusedTransformMaxK = 256;
+// single calls fuse only with at least this many workgroups (two per CU)
+constexpr int kFusedMinBlocks = 512;
 // Radix FFT transform (power-of-two m, 128 <= m <= 1024, FFT length
 // L = 2^log2l = 2m; fft_points(L) spectral points per workgroup: 8, or the
 // 4096/L points of one pass of its 256 threads) and its tables (2m

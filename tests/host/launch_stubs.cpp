@@ -28,6 +28,8 @@ hipError_t launch_prep(const TableSrcInline&, int, int, int64_t, const PrepSrcIn
 }
 hipError_t launch_transform(int, const PrepSrcInline&, int, hipStream_t) { reached("transform"); }
 hipError_t launch_transform(int, const PrepSrcArray&, int, hipStream_t) { reached("transform"); }
+hipError_t launch_center_transform(int, const PrepSrcInline&, int, hipStream_t) { reached("center_transform"); }
+hipError_t launch_center_transform(int, const PrepSrcArray&, int, hipStream_t) { reached("center_transform"); }
 hipError_t launch_fft_tables(const TableSrcInline&, int64_t, hipStream_t) { reached("fft_tables"); }
 hipError_t launch_fft_transform(int, int, const PrepSrcInline&, int, hipStream_t) { reached("fft_transform"); }
 hipError_t launch_corr(int, int, int, const CorrJob&, int64_t, hipStream_t) { reached("corr"); }
