@@ -801,9 +801,9 @@ corr2d_status corr2d_batched_plan(corr2d_plan_t* out, const corr2d_desc* common,
     p->ws_bytes = off;
     if (log_enabled()) {
         std::fprintf(stderr, "corr2d: batched plan %s items=%lld distinct_m=%zu tiles=%lld out_elements=%lld "
-                             "workspace=%zu B tune: %s\n",
+                             "centring=%s workspace=%zu B tune: %s\n",
                      prec_name(common->prec), (long long)count, p->distinct_m.size(), (long long)p->total_tiles,
-                     (long long)p->out_elements, p->ws_bytes, tune_source());
+                     (long long)p->out_elements, p->fused_center ? "fused" : "separate", p->ws_bytes, tune_source());
         for (const auto& gr : p->groups)
             std::fprintf(stderr, "corr2d:   tile %d (%dx%d): %d data sets, %lld tiles, one persistent launch\n",
                          gr.tile.id, 32 * gr.tile.fm, 32 * gr.tile.fn, gr.count, (long long)gr.tiles);

@@ -324,6 +324,34 @@ def test_plan_log():
     assert r.returncode == 0 and "corr2d:" not in r.stderr
 
 
+def test_fused_centring_decision():
+    """The table-product transform takes the centring into its own kernel for
+    m <= 256 in every format but FP64, in single calls only when that launch
+    has at least 512 workgroups (one per 64 spectral points and 256 transform
+    rows), in batched plans whenever every set has m <= 256."""
+    import subprocess
+    import sys
+    code = ("from paper_1808_00685_amd import binding as B\n"
+            "for kw in (dict(m=200, n1=16384, prec='split_f16'), dict(m=64, n1=4096, prec='f32'),\n"
+            "           dict(m=300, n1=16384, prec='split_f16'), dict(m=200, n1=16384, prec='f64'),\n"
+            "           dict(m=100, n1=32768, prec='fp8_e4m3')):\n"
+            "    _, h = B.corr2d_plan(B.corr2d_desc_init(**kw))\n"
+            "    B.corr2d_plan_destroy(h)\n"
+            "for m2 in (200, 300):\n"
+            "    items = [B.corr2d_item(m=20, n=300), B.corr2d_item(m=m2, n=700, out_offset=90000)]\n"
+            "    _, h = B.corr2d_batched_plan(B.corr2d_desc_init(prec='f32'), items)\n"
+            "    B.corr2d_plan_destroy(h)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CORR2D_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    plans = [ln for ln in r.stderr.splitlines() if ln.startswith("corr2d: plan")]
+    assert [("centring fused" in ln) for ln in plans] == [True, False, False, False, True]
+    batched = [ln for ln in r.stderr.splitlines() if ln.startswith("corr2d: batched plan")]
+    assert ["centring=fused" in batched[0], "centring=separate" in batched[1]] == [True, True]
+
+
 def test_compute_calls_reject_bad_arguments_before_device_work():
     d = B.corr2d_desc_init(m=11, n1=64)
     _, h = B.corr2d_plan(d)

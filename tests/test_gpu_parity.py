@@ -576,6 +576,30 @@ def test_reference_spectrum_is_the_mean(gpu, prec, m, n, in32):
     assert rel_fro(_np(r.psi), psi_o) <= TOL[prec]
 
 
+def test_fused_centring_single_call(gpu):
+    """The centring fused into the table-product transform (m <= 256 and a
+    launch of >= 512 workgroups: m = 200, n = 16384, two row tiles per 64
+    spectral points) writes the oracle's FP64 mean (Eq. (ref)), and sampled
+    entries of Phi and Psi (Eqs. (disHTsyn), (disHTasyn)) match the oracle's."""
+    import torch
+    m, n = 200, 16384
+    S = _rand(m, n, 720)
+    r = B.corr2d(_t(S, gpu), prec="split_f16", layout="upper_aligned")
+    torch.cuda.synchronize()
+    assert r.plan.info.transform == 0
+    _, mean_o = oracle.dynamic(S)
+    assert np.abs(_np(r.ref1) - mean_o).max() <= _mean_tol(m, S)
+    rng = np.random.default_rng(721)
+    i = rng.integers(0, n, 4000)
+    j = rng.integers(0, n, 4000)
+    i, j = np.minimum(i, j), np.maximum(i, j)
+    i[:64], j[:64] = np.arange(64) * 255, n - 1 - np.arange(64)   # first and last column blocks
+    idx = torch.as_tensor(B.upper_aligned_index(i, j, n), device=gpu)
+    phi_o, psi_o = oracle.corr2d_entries(S, i, j)
+    assert rel_fro(_np(r.phi[idx]), phi_o) <= TOL["split_f16"]
+    assert rel_fro(_np(r.psi[idx]), psi_o) <= TOL["split_f16"]
+
+
 @pytest.mark.parametrize("m", [32, 256])
 def test_reference_spectra_hetero_given_and_mean(gpu, m):
     """Heterocorrelation with a caller's ref1 and the mean for set 2: Ref1
