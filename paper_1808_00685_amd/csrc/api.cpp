@@ -384,6 +384,11 @@ int transform_blocks(const Geo& g, int prec) {
     if (prec == CORR2D_PREC_F64) return (int)((g.n_pad / kTransformTile) * (g.rows_pad / kTransformTile));
     return (int)((g.n_pad / 64) * ((g.rows_pad + 255) / 256));
 }
+// Workgroups of the transform launch: the fused centring kernel has one per
+// 64 spectral points (it runs the row tiles in turn).
+int prep_blocks(const Geo& g, int prec, bool fused) {
+    return fused ? (int)(g.n_pad / 64) : transform_blocks(g, prec);
+}
 
 // The radix FFT transform (FP64 for the FP64 path, else FP32) serves
 // power-of-two m in [128, 1024]: the Fourier basis, and the time basis with
@@ -609,10 +614,10 @@ corr2d_status corr2d_plan(corr2d_plan_t* out, const corr2d_desc* d) {
     const bool t64 = d->prec == CORR2D_PREC_F64;
     p->g1 = geometry(d->m, d->n1, d->prec);
     p->fft = use_fft(&p->d, d->m);
-    // a single call fuses the centring only when the fused launch fills the
-    // GPU: it has one workgroup per 64 spectral points (and 256 transform
-    // rows), where the separate centring has one per 32; at m = 64, n = 4096
-    // (64 workgroups) fusing cost 3 us per call
+    // a single call fuses the centring only when the transform has enough
+    // work to fill the GPU: at least 512 tiles of 64 spectral points x 256
+    // transform rows (the separate centring has a workgroup per 32 points);
+    // at m = 64, n = 4096 (64 tiles) fusing cost 3 us per call
     const int fused_blocks = transform_blocks(p->g1, d->prec) +
                              (hetero ? transform_blocks(geometry(d->m, d->n2, d->prec), d->prec) : 0);
     p->fused_center = !p->fft && d->prec != CORR2D_PREC_F64 && p->g1.kt <= kFusedTransformMaxK &&
@@ -956,7 +961,7 @@ corr2d_status corr2d_homo(corr2d_plan_t p, const void* y, const double* ref, voi
         ps.blocks0 = fft_blocks(p->g1);
         e = launch_fft_transform(p->d.prec, fft_log2(p->g1.m), ps, ps.blocks0, s);
     } else {
-        ps.blocks0 = transform_blocks(p->g1, p->d.prec);
+        ps.blocks0 = prep_blocks(p->g1, p->d.prec, p->fused_center);
         e = p->fused_center ? launch_center_transform(p->d.prec, ps, ps.blocks0, s)
                             : launch_transform(p->d.prec, ps, ps.blocks0, s);
     }
@@ -1023,8 +1028,8 @@ corr2d_status corr2d_hetero(corr2d_plan_t p, const void* y1, const double* ref1,
         ps.blocks0 = fft_blocks(p->g1);
         e = launch_fft_transform(p->d.prec, fft_log2(p->g1.m), ps, ps.blocks0 + fft_blocks(p->g2), s);
     } else {
-        ps.blocks0 = transform_blocks(p->g1, p->d.prec);
-        const int nb = ps.blocks0 + transform_blocks(p->g2, p->d.prec);
+        ps.blocks0 = prep_blocks(p->g1, p->d.prec, p->fused_center);
+        const int nb = ps.blocks0 + prep_blocks(p->g2, p->d.prec, p->fused_center);
         e = p->fused_center ? launch_center_transform(p->d.prec, ps, nb, s) : launch_transform(p->d.prec, ps, nb, s);
     }
     if (e != hipSuccess) return device_fail(e, "transform launch");
@@ -1114,7 +1119,7 @@ void fill_blob(corr2d_plan_s* p, const void* y_base, void* phi_base, void* psi_b
         cs[r] = cb;
         cb += center_blocks(I.g);
         xs[r] = xb;
-        xb += transform_blocks(I.g, p->d.prec);
+        xb += prep_blocks(I.g, p->d.prec, p->fused_center);
         void* ph = (char*)phi_base + I.it.out_offset * osz;
         void* ps = (char*)psi_base + I.it.out_offset * osz;
         cj[r] = make_corr_job(p, I.g, I.s, I.g, I.s, ws, ph, ps, true, I.c, I.tile, I.it.n,
@@ -1201,7 +1206,7 @@ corr2d_status enqueue_sequential(corr2d_plan_s* p, const void* y_base, void* phi
         ps.blocks0 = center_blocks(I.g);
         if (!p->fused_center) e = launch_center(ps, ps.blocks0, s);
         if (e != hipSuccess) return device_fail(e, "center launch");
-        ps.blocks0 = transform_blocks(I.g, p->d.prec);
+        ps.blocks0 = prep_blocks(I.g, p->d.prec, p->fused_center);
         e = p->fused_center ? launch_center_transform(p->d.prec, ps, ps.blocks0, s)
                             : launch_transform(p->d.prec, ps, ps.blocks0, s);
         if (e != hipSuccess) return device_fail(e, "transform launch");

@@ -725,9 +725,9 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
 // scales, and keeps the centred columns in LDS as the GEMM's B operand, so
 // the centred spectra never go through HBM.  The arithmetic per value is the
 // separate centring kernel's (FP64 difference and scaling, one rounding to
-// FP32); only the order of the FP64 column sums differs.  Workgroups of the
-// same points and another row tile repeat the centring; the first row tile
-// writes the reference, the scales and nothing else of it.
+// FP32); only the order of the FP64 column sums differs.  One workgroup per
+// 64 spectral points: it centres them once and then runs every row tile of
+// 256 transform rows over them in turn (m up to 128 has one, up to 256 two).
 template <int P, class Src>
 __global__ __launch_bounds__(256) void center_transform32_kernel(Src src) {
     constexpr int YP = kFusedTransformMaxK + 4;   // LDS row pitch of a centred column (floats)
@@ -737,9 +737,8 @@ __global__ __launch_bounds__(256) void center_transform32_kernel(Src src) {
     int lb;
     const PrepJob J = src.get(blockIdx.x, lb);
     const int rtiles = (J.rows_pad + kT32Cols - 1) / kT32Cols;
-    const int bi = lb / rtiles, br = lb % rtiles;
     const int tid = threadIdx.x;
-    const int64_t i0 = (int64_t)bi * 64;
+    const int64_t i0 = (int64_t)lb * 64;
 
     // centring: thread (g, c) takes rows g, g + 4, ... of column i0 + c, all
     // loaded at once into registers (the LDS tile already limits the kernel
@@ -803,62 +802,63 @@ __global__ __launch_bounds__(256) void center_transform32_kernel(Src src) {
             }
             s_scale[0][c] = J.sA ? sa : 0.0f;
             s_scale[1][c] = J.sB ? sb : 0.0f;
-            if (br == 0) {
-                if (valid && J.ref_out) J.ref_out[col] = mean;
-                if (J.sA) J.sA[col] = sa;
-                if (J.sB) J.sB[col] = sb;
-            }
+            if (valid && J.ref_out) J.ref_out[col] = mean;
+            if (J.sA) J.sA[col] = sa;
+            if (J.sB) J.sB[col] = sb;
         }
         __syncthreads();
     }
 
     const int lane = tid & 63, wave = tid >> 6;
     const int row16 = lane & 15, kg = lane >> 4;
-    const int64_t r0 = (int64_t)br * kT32Cols + wave * 64;
-    if (r0 >= J.rows_pad) return;   // no barrier follows
     const float* T = (const float*)J.table;
-    const float* yrow[4];
-    const float* trow[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        yrow[a] = ytile + (a * 16 + row16) * YP + kg * 4;
-        trow[a] = T + (r0 + a * 16 + row16) * J.kt + kg * 4;
-    }
-    f4 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < J.kt; k0 += 16) {
-        f4 fa[4], fb[4];
+    // no barrier below: the LDS tile and the scales are only read from here on
+    for (int br = 0; br < rtiles; ++br) {
+        const int64_t r0 = (int64_t)br * kT32Cols + wave * 64;
+        if (r0 >= J.rows_pad) break;
+        const float* yrow[4];
+        const float* trow[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            fa[a] = *(const f4*)(yrow[a] + k0);
-            fb[a] = *(const f4*)(trow[a] + k0);
+            yrow[a] = ytile + (a * 16 + row16) * YP + kg * 4;
+            trow[a] = T + (r0 + a * 16 + row16) * J.kt + kg * 4;
+        }
+        f4 acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < J.kt; k0 += 16) {
+            f4 fa[4], fb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                fa[a] = *(const f4*)(yrow[a] + k0);
+                fb[a] = *(const f4*)(trow[a] + k0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b][s], fa[a][s], acc[a][b], 0, 0, 0);
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int b = 0; b < 4; ++b) {
+            const int64_t rb0 = r0 + b * 16;
+            if (rb0 >= 2 * (int64_t)J.kp) continue;
+            const bool isB = rb0 >= J.kp;
+            if (isB && !J.need_b) continue;
+            const int64_t k = (isB ? rb0 - J.kp : rb0) + kg * 4;
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[b][s], fa[a][s], acc[a][b], 0, 0, 0);
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int64_t rb0 = r0 + b * 16;
-        if (rb0 >= 2 * (int64_t)J.kp) continue;
-        const bool isB = rb0 >= J.kp;
-        if (isB && !J.need_b) continue;
-        const int64_t k = (isB ? rb0 - J.kp : rb0) + kg * 4;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int il = a * 16 + row16;
-            const int64_t i = i0 + il;
-            const float sc = s_scale[isB ? 1 : 0][il];
-            const float x[4] = {acc[a][b][0] * sc, acc[a][b][1] * sc, acc[a][b][2] * sc, acc[a][b][3] * sc};
-            const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
-            store_operand4<P>(isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx, x);
+            for (int a = 0; a < 4; ++a) {
+                const int il = a * 16 + row16;
+                const int64_t i = i0 + il;
+                const float sc = s_scale[isB ? 1 : 0][il];
+                const float x[4] = {acc[a][b][0] * sc, acc[a][b][1] * sc, acc[a][b][2] * sc, acc[a][b][3] * sc};
+                const int64_t idx = blocked_layout(P) ? blocked_index(i, k, J.kp) : i * J.kp + k;
+                store_operand4<P>(isB ? J.B0 : J.A0, isB ? J.B1 : J.A1, idx, x);
+            }
         }
     }
 }
