@@ -501,3 +501,29 @@ def test_noalloc_rejects_before_device_work():
     assert b"fixed scratch" in L.corr2d_last_error()
     fits = B.Plan(m=256, n1=16384, n2=0, prec="split_bf16", out_layout="upper_aligned")
     assert fits.ws_bytes <= B.NOALLOC_SCRATCH_BYTES
+
+
+def test_batched_plan_one_tile_shape():
+    """A batched plan runs every data set in one tile shape, the tuned shape
+    of the set with the largest m n^2, so its contraction is one persistent
+    launch even where single calls of its sets would take different shapes."""
+    import subprocess
+    import sys
+    code = ("from paper_1808_00685_amd import binding as B\n"
+            "for kw in (dict(m=20, n1=300, prec='f32'), dict(m=128, n1=16000, prec='f32')):\n"
+            "    _, h = B.corr2d_plan(B.corr2d_desc_init(**kw))\n"
+            "    print('single', B.corr2d_plan_get_info(h).tile)\n"
+            "    B.corr2d_plan_destroy(h)\n"
+            "items = [B.corr2d_item(m=20, n=300), B.corr2d_item(m=128, n=16000, out_offset=90000)]\n"
+            "_, h = B.corr2d_batched_plan(B.corr2d_desc_init(prec='f32'), items)\n"
+            "B.corr2d_plan_destroy(h)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CORR2D_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    singles = [int(ln.split()[1]) for ln in r.stdout.splitlines() if ln.startswith("single")]
+    assert len(set(singles)) == 2
+    launches = [ln for ln in r.stderr.splitlines() if "one persistent launch" in ln]
+    assert len(launches) == 1
+    assert f"tile {singles[1]} " in launches[0] and "2 data sets" in launches[0]
