@@ -720,10 +720,10 @@ __global__ __launch_bounds__(256) void transform32_kernel(Src src) {
 // Centring fused into the FP32 transform GEMM, for short spectra (kt <=
 // kFusedTransformMaxK): each workgroup centres its own 64 spectral points
 // (the mean over the m perturbation steps in FP64, or the given reference,
-// Sec. 2 Eqs. (dynspec), (ref)), applies
-// the result scaling sigma^-alpha, takes each column's norm for the per-band
-// scales, and keeps the centred columns in LDS as the GEMM's B operand, so
-// the centred spectra never go through HBM.  The arithmetic per value is the
+// Sec. 2 Eqs. (dynspec), (ref)), applies the result scaling sigma^-alpha,
+// takes each column's norm for the per-band scales, and keeps the centred
+// columns in LDS as the GEMM's B operand, so the centred spectra never go
+// through HBM.  The arithmetic per value is the
 // separate centring kernel's (FP64 difference and scaling, one rounding to
 // FP32); only the order of the FP64 column sums differs.  One workgroup per
 // 64 spectral points: it centres them once and then runs every row tile of
